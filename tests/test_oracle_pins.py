@@ -1,0 +1,398 @@
+"""Pins for the FP64 CPU oracle against things other than itself.
+
+Each test ties the oracle to an exact closed form, a library routine implementing the same
+mathematics independently (torch.nn.functional.grid_sample, autograd, torch.optim.Adam), finite
+differences, or an invariant the paper's equations imply. A plausible slip in the oracle (a
+dropped term, a sign, a transposed operand, a wrong index or depth order) breaks at least one.
+"""
+from fractions import Fraction as Fr
+import math
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+import oracle
+from paper_2602_22625_amd import synth
+
+
+def _scene(seed, N=12, H=40, W=40, with_star=True, log_s=math.log(7.0)):
+    g = np.random.default_rng(seed)
+    atl = [synth.soft_disk(32)]
+    if with_star:
+        atl.append(synth.make_atlas("ss64x16")[0][::2, ::2].copy())  # a 32x32 star
+        atl.append(synth.make_atlas("ss64x16")[9][::2, ::2].copy())  # a 32x32 stroke
+    atlas = np.stack(atl).astype(np.float64)
+    p = np.zeros((N, 8))
+    p[:, 0] = g.uniform(0, W, N)
+    p[:, 1] = g.uniform(0, H, N)
+    p[:, 2] = g.normal(log_s, 0.3, N)
+    p[:, 3] = g.uniform(0, 2 * math.pi, N)
+    p[:, 4] = g.normal(0.5, 1.0, N)
+    p[:, 5:] = g.normal(0, 1.5, (N, 3))
+    idx = g.integers(0, atlas.shape[0], N).astype(np.int32)
+    return p, idx, atlas
+
+
+# ------------------------------------------------------------------------------------------
+# P-UNIT: an axis-aligned, unit-scale, opaque primitive reproduces its bitmap
+# ------------------------------------------------------------------------------------------
+def test_unit_scale_bitwise_3x3():
+    """Eq. (1)-(2) with theta=0, s=1 on a 3x3 bitmap map pixel offsets to integer texels exactly,
+    so the rendered image must equal the bitmap bit for bit (sigma(40) == 1 in float64)."""
+    g = np.random.default_rng(1)
+    bm = g.uniform(0, 1, (3, 3))
+    H, W, ox, oy = 9, 11, 4, 3
+    p = np.array([[ox + 1.0, oy + 1.0, 0.0, 0.0, 40.0, 40.0, 40.0, 40.0]])
+    img, alp = oracle.render(p, [0], bm[None], H, W, bg=(0, 0, 0), alpha_max=1.0)
+    exp_img = np.zeros((H, W))
+    exp_img[oy:oy + 3, ox:ox + 3] = bm
+    for c in range(3):
+        assert np.array_equal(img[c], exp_img)
+    assert np.array_equal(alp, exp_img)
+
+
+@pytest.mark.parametrize("theta,transform", [(0.0, lambda b: b),
+                                             (math.pi / 2, lambda b: b[::-1, :].T),
+                                             (math.pi, lambda b: b[::-1, ::-1])])
+def test_unit_scale_33(theta, transform):
+    """33x33 bitmap at s=16 (one texel per pixel). A rotation by theta turns the bitmap by theta
+    about its centre (canvas y points down, so +pi/2 maps bitmap column u to canvas row)."""
+    g = np.random.default_rng(2)
+    bm = g.uniform(0, 1, (33, 33))
+    H, W, ox, oy = 40, 45, 5, 3
+    p = np.array([[ox + 16.0, oy + 16.0, math.log(16.0), theta, 40.0, 40.0, 40.0, 40.0]])
+    img, alp = oracle.render(p, [0], bm[None], H, W, bg=(0, 0, 0), alpha_max=1.0)
+    exp_img = np.zeros((H, W))
+    # theta = pi/2: canvas pixel (ox+q, oy+r) has dx = q-16, dy = r-16, so u = dy/s, v = -dx/s,
+    # i.e. bitmap row V = 32 - q and column U = r:  canvas[oy+r, ox+q] = bm[32-q, r].
+    exp_img[oy:oy + 33, ox:ox + 33] = transform(bm)
+    assert np.max(np.abs(alp - exp_img)) < 1e-12
+    assert np.max(np.abs(img[1] - exp_img)) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# Exact rational closed form (hand evaluation of Eqs. 1-5, S1-S3 with Python Fractions)
+# ------------------------------------------------------------------------------------------
+def test_exact_rational_two_layers():
+    """Two unit-scale layers at half-texel offsets (bilinear weights 1/2), nu = c = 0 so every
+    sigmoid is exactly 1/2, alpha_max = 3/4, texels k/8. The oracle must agree with exact
+    rational arithmetic to float64 rounding."""
+    bmA = [[Fr(1, 8) * ((3 * r + 5 * q) % 9) for q in range(3)] for r in range(3)]
+    bmB = [[Fr(1, 8) * ((7 * r + 2 * q + 1) % 9) for q in range(3)] for r in range(3)]
+    amax = Fr(3, 4)
+    bg = (Fr(1, 4), Fr(1, 2), Fr(1, 1))
+    # layer 0 centre (3.5, 2.0): U = dx + 1 (half-integers), V = dy + 1 (integers)
+    # layer 1 centre (4.0, 3.5)
+    cen = [(Fr(7, 2), Fr(2)), (Fr(4), Fr(7, 2))]
+    bms = [bmA, bmB]
+    H, W = 7, 8
+
+    def tex(bm, r, c):
+        return bm[r][c] if 0 <= r < 3 and 0 <= c < 3 else Fr(0)
+
+    def M(bm, U, V):
+        import math as m
+        u0, v0 = m.floor(U), m.floor(V)
+        if u0 < -1 or u0 > 2 or v0 < -1 or v0 > 2:
+            return Fr(0)
+        wu, wv = U - u0, V - v0
+        return ((1 - wu) * (1 - wv) * tex(bm, v0, u0) + wu * (1 - wv) * tex(bm, v0, u0 + 1)
+                + (1 - wu) * wv * tex(bm, v0 + 1, u0) + wu * wv * tex(bm, v0 + 1, u0 + 1))
+
+    exp = np.zeros((3, H, W))
+    expA = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            T = Fr(1)
+            C = [Fr(0)] * 3
+            for k in range(2):
+                U = (x - cen[k][0]) + 1
+                V = (y - cen[k][1]) + 1
+                a = amax * Fr(1, 2) * M(bms[k], U, V)
+                for j in range(3):
+                    C[j] += T * a * Fr(1, 2)
+                T *= (1 - a)
+            for j in range(3):
+                exp[j, y, x] = float(C[j] + T * bg[j])
+            expA[y, x] = float(1 - T)
+    p = np.array([[3.5, 2.0, 0, 0, 0, 0, 0, 0], [4.0, 3.5, 0, 0, 0, 0, 0, 0]], dtype=np.float64)
+    atlas = np.array([[[float(v) for v in row] for row in bmA],
+                      [[float(v) for v in row] for row in bmB]])
+    img, alp = oracle.render(p, [0, 1], atlas, H, W, bg=[float(b) for b in bg], alpha_max=0.75)
+    assert np.max(np.abs(img - exp)) < 1e-15
+    assert np.max(np.abs(alp - expA)) < 1e-15
+
+
+# ------------------------------------------------------------------------------------------
+# P-LIB: the sampler equals torch grid_sample(align_corners=True, zeros) and its autograd
+# ------------------------------------------------------------------------------------------
+def _torch_alg3(p, idx, atlas, H, W, bg, alpha_max):
+    """Supp. Alg. 3 in float64 PyTorch: every primitive over the full canvas, bilinear sampling by
+    grid_sample (zero padding; align_corners=True is exactly Eq. 2), then the background."""
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    I = torch.zeros(3, H, W, dtype=torch.float64)
+    T = torch.ones(H, W, dtype=torch.float64)
+    at = torch.as_tensor(atlas, dtype=torch.float64)
+    for i in range(p.shape[0]):
+        s = torch.exp(p[i, 2])
+        c, sn = torch.cos(p[i, 3]), torch.sin(p[i, 3])
+        dx, dy = xs - p[i, 0], ys - p[i, 1]
+        u = (c * dx + sn * dy) / s
+        v = (-sn * dx + c * dy) / s
+        grid = torch.stack([u, v], dim=-1)[None]
+        m = F.grid_sample(at[int(idx[i])][None, None], grid, mode="bilinear",
+                          padding_mode="zeros", align_corners=True)[0, 0]
+        a = alpha_max * torch.sigmoid(p[i, 4]) * m
+        I = I + T * a * torch.sigmoid(p[i, 5:8])[:, None, None]
+        T = T * (1 - a)
+    bg = torch.as_tensor(np.asarray(bg, dtype=np.float64))
+    if bg.numel() == 3:
+        bg = bg.reshape(3, 1, 1)
+    return I + T * bg, 1 - T
+
+
+def test_sampler_matches_grid_sample():
+    p, idx, atlas = _scene(3, N=1)
+    p[0, :2] = (19.3, 21.6)
+    p[0, 4:] = 40.0  # sigma == 1: image == M
+    idx[:] = 1       # a star: sharp anti-aliased edges
+    img, alp = oracle.render(p, idx, atlas, 40, 40, bg=(0, 0, 0), alpha_max=1.0)
+    ref, _ = _torch_alg3(torch.tensor(p), idx, atlas, 40, 40, (0, 0, 0), 1.0)
+    assert np.max(np.abs(alp - ref[0].numpy())) < 1e-13
+    assert (alp > 0).sum() > 100
+
+
+@pytest.mark.parametrize("seed,alpha_max,per_pixel_bg", [(4, 1.0, False), (5, 0.7, True)])
+def test_backward_matches_autograd_of_alg3(seed, alpha_max, per_pixel_bg):
+    """Gradients of L = sum(wI * I) + sum(wA * A): hand-derived backward (Eq. 7, S4, S5) vs
+    autograd through grid_sample (an independent derivation)."""
+    H, W = 36, 44
+    p, idx, atlas = _scene(seed, N=14, H=H, W=W)
+    g = np.random.default_rng(seed + 100)
+    bg = g.uniform(0, 1, (3, H, W)) if per_pixel_bg else g.uniform(0, 1, 3)
+    wI = g.standard_normal((3, H, W))
+    wA = g.standard_normal((H, W))
+    img, alp = oracle.render(p, idx, atlas, H, W, bg=bg, alpha_max=alpha_max)
+    grad = oracle.render_backward(p, idx, atlas, H, W, wI, wA, bg=bg, alpha_max=alpha_max)
+    pt = torch.tensor(p, requires_grad=True)
+    I, A = _torch_alg3(pt, idx, atlas, H, W, bg, alpha_max)
+    assert np.max(np.abs(I.detach().numpy() - img)) < 1e-13
+    assert np.max(np.abs(A.detach().numpy() - alp)) < 1e-13
+    L = (torch.tensor(wI) * I).sum() + (torch.tensor(wA) * A).sum()
+    L.backward()
+    ref = pt.grad.numpy()
+    for j in range(8):
+        scale = max(np.max(np.abs(ref[:, j])), 1e-12)
+        assert np.max(np.abs(grad[:, j] - ref[:, j])) / scale < 1e-10, j
+
+
+def test_backward_matches_autograd_c0():
+    """The c0 workload (64 soft disks on 128x128, white background)."""
+    d = synth.make_workload("c0")
+    p = d["params"].astype(np.float64)
+    H = W = 128
+    g = np.random.default_rng(11)
+    wI = g.standard_normal((3, H, W))
+    grad = oracle.render_backward(p, d["idx"], d["atlas"], H, W, wI, None)
+    pt = torch.tensor(p, requires_grad=True)
+    I, _ = _torch_alg3(pt, d["idx"], d["atlas"].astype(np.float64), H, W, (1, 1, 1), 1.0)
+    (torch.tensor(wI) * I).sum().backward()
+    ref = pt.grad.numpy()
+    for j in range(8):
+        scale = np.max(np.abs(ref[:, j]))
+        assert np.max(np.abs(grad[:, j] - ref[:, j])) / scale < 1e-10, j
+
+
+# ------------------------------------------------------------------------------------------
+# P-FD: gradients match central finite differences
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,alpha_max", [(21, 1.0), (22, 0.8)])
+def test_backward_matches_finite_differences(seed, alpha_max):
+    H, W = 30, 34
+    p, idx, atlas = _scene(seed, N=10, H=H, W=W, log_s=math.log(6.0))
+    g = np.random.default_rng(seed + 7)
+    bg = g.uniform(0, 1, 3)
+    wI = g.standard_normal((3, H, W))
+    wA = g.standard_normal((H, W))
+
+    def L(pp):
+        img, alp = oracle.render(pp, idx, atlas, H, W, bg=bg, alpha_max=alpha_max)
+        return float(np.sum(wI * img) + np.sum(wA * alp))
+
+    grad = oracle.render_backward(p, idx, atlas, H, W, wI, wA, bg=bg, alpha_max=alpha_max)
+    fd = np.zeros_like(p)
+    h = 1e-7
+    for k in range(p.shape[0]):
+        for j in range(8):
+            pp = p.copy()
+            pp[k, j] += h
+            lp = L(pp)
+            pp[k, j] -= 2 * h
+            lm = L(pp)
+            fd[k, j] = (lp - lm) / (2 * h)
+    for j in range(8):
+        scale = np.max(np.abs(fd[:, j]))
+        assert scale > 0
+        assert np.max(np.abs(grad[:, j] - fd[:, j])) / scale < 1e-5, (j, grad[:, j], fd[:, j])
+
+
+# ------------------------------------------------------------------------------------------
+# P-ZERO, P-MONO, P-CLOSED: invariants of Eqs. (3)-(5)
+# ------------------------------------------------------------------------------------------
+def test_zero_opacity_contributes_nothing():
+    H, W = 40, 40
+    p, idx, atlas = _scene(31, N=10, H=H, W=W)
+    atlas = np.concatenate([atlas, np.zeros((1,) + atlas.shape[1:])])
+    g = np.random.default_rng(5)
+    wI = g.standard_normal((3, H, W))
+    wA = g.standard_normal((H, W))
+    base_img, base_a = oracle.render(p, idx, atlas, H, W)
+    base_g = oracle.render_backward(p, idx, atlas, H, W, wI, wA)
+    # insert a sigma(nu) == 0 layer at depth 4 and an all-zero bitmap at depth 7, both on-canvas
+    z1 = np.array([[20.0, 20.0, math.log(9.0), 0.3, -1000.0, 0.1, 0.2, 0.3]])
+    z2 = np.array([[18.0, 22.0, math.log(9.0), 1.3, 3.0, 0.1, 0.2, 0.3]])
+    p2 = np.concatenate([p[:4], z1, p[4:6], z2, p[6:]])
+    idx2 = np.concatenate([idx[:4], [0], idx[4:6], [atlas.shape[0] - 1], idx[6:]]).astype(np.int32)
+    img, a = oracle.render(p2, idx2, atlas, H, W)
+    gr = oracle.render_backward(p2, idx2, atlas, H, W, wI, wA)
+    assert np.array_equal(img, base_img) and np.array_equal(a, base_a)
+    keep = [i for i in range(p2.shape[0]) if i not in (4, 7)]
+    assert np.array_equal(gr[keep], base_g)
+    assert np.all(gr[4] == 0.0) and np.all(gr[7] == 0.0)
+
+
+def test_transmittance_monotone_and_partition_of_unity():
+    d = synth.make_workload("c0")
+    g = np.random.default_rng(3)
+    seen = 0
+    for _ in range(400):
+        px, py = int(g.integers(0, 128)), int(g.integers(0, 128))
+        ks, al, Ts, TN = oracle.pixel_trace(d["params"], d["idx"], d["atlas"], px, py)
+        if len(ks) == 0:
+            continue
+        seen += len(ks)
+        assert np.all(np.diff(ks) > 0)                       # front-to-back = index order
+        assert Ts[0] == 1.0                                  # T_0 = 1 (Eq. 4)
+        allT = np.append(Ts, TN)
+        assert np.all(np.diff(allT) <= 0) and np.all(allT >= 0) and np.all(allT <= 1)
+        assert abs(np.sum(Ts * al) + TN - 1.0) < 1e-13      # sum_k T_k alpha_k + T_N = 1
+    assert seen > 40
+
+
+def test_uniform_colour_equal_to_background_gives_background():
+    d = synth.make_workload("c0")
+    p = d["params"].astype(np.float64).copy()
+    p[:, 5:] = 0.0  # sigma(0) = 1/2 exactly
+    img, _ = oracle.render(p, d["idx"], d["atlas"], 128, 128, bg=(0.5, 0.5, 0.5))
+    assert np.max(np.abs(img - 0.5)) < 1e-15
+
+
+def test_front_back_split():
+    """render(all, b) = render(front, b=0) + T_front * render(back, b): the over operator is
+    associative, with T_front = 1 - A_front."""
+    H, W = 40, 40
+    p, idx, atlas = _scene(41, N=16, H=H, W=W)
+    bg = (0.2, 0.9, 0.4)
+    full, fa = oracle.render(p, idx, atlas, H, W, bg=bg)
+    front, fra = oracle.render(p[:7], idx[:7], atlas, H, W, bg=(0, 0, 0))
+    back, ba = oracle.render(p[7:], idx[7:], atlas, H, W, bg=bg)
+    assert np.max(np.abs(full - (front + (1 - fra) * back))) < 1e-14
+    assert np.max(np.abs((1 - fa) - (1 - fra) * (1 - ba))) < 1e-14
+
+
+def test_one_and_two_layer_closed_forms():
+    """I = a0 c0 + (1-a0)(a1 c1 + (1-a1) b) with alpha maps taken from single-layer renders."""
+    H, W = 40, 40
+    p, idx, atlas = _scene(51, N=2, H=H, W=W)
+    p[:, 0], p[:, 1] = [18, 22], [20, 17]
+    bg = np.array([0.3, 0.6, 0.9])
+    alphas = []
+    for k in range(2):
+        q = p[k:k + 1].copy()
+        q[0, 5:] = 40.0  # colour 1, background 0  ->  image = alpha_k
+        _, a = oracle.render(q, idx[k:k + 1], atlas, H, W, bg=(0, 0, 0))
+        alphas.append(a)
+    a0, a1 = alphas
+    c = 1 / (1 + np.exp(-p[:, 5:]))
+    img, _ = oracle.render(p, idx, atlas, H, W, bg=bg)
+    exp = (a0 * c[0][:, None, None]
+           + (1 - a0) * (a1 * c[1][:, None, None] + (1 - a1) * bg[:, None, None]))
+    assert np.max(np.abs(img - exp)) < 1e-14
+    assert (a0 * a1 > 0.05).sum() > 10  # the two layers really overlap
+
+
+def test_depth_order_is_index_order():
+    """Swapping two overlapping layers changes the image (index 0 is in front)."""
+    H, W = 30, 30
+    p, idx, atlas = _scene(61, N=2, H=H, W=W)
+    p[:, 0], p[:, 1] = 15, 15
+    img, _ = oracle.render(p, idx, atlas, H, W)
+    img2, _ = oracle.render(p[::-1].copy(), idx[::-1].copy(), atlas, H, W)
+    assert np.max(np.abs(img - img2)) > 1e-3
+
+
+def test_crop_equals_full_and_backward_is_additive_over_pixels():
+    H, W = 36, 40
+    p, idx, atlas = _scene(71, N=12, H=H, W=W)
+    g = np.random.default_rng(9)
+    wI = g.standard_normal((3, H, W))
+    full, fa = oracle.render(p, idx, atlas, H, W)
+    crop = (5, 7, 21, 17)
+    x0, y0, w, h = crop
+    cimg, ca = oracle.render(p, idx, atlas, H, W, crop=crop)
+    assert np.array_equal(cimg, full[:, y0:y0 + h, x0:x0 + w])
+    gfull = oracle.render_backward(p, idx, atlas, H, W, wI)
+    m = np.zeros((3, H, W))
+    m[:, y0:y0 + h, x0:x0 + w] = 1
+    gin = oracle.render_backward(p, idx, atlas, H, W, wI[:, y0:y0 + h, x0:x0 + w], crop=crop)
+    gout = oracle.render_backward(p, idx, atlas, H, W, wI * (1 - m))
+    assert np.max(np.abs(gin + gout - gfull)) < 1e-12 * max(1.0, np.max(np.abs(gfull)))
+
+
+def test_support_pair_count_bruteforce_small():
+    """Tiny case counted by hand-written loops in Python."""
+    p, idx, atlas = _scene(81, N=5, H=20, W=24, log_s=math.log(4.0))
+    n = oracle.support_pairs_bruteforce(p, 32, 32, 20, 24)
+    cnt = 0
+    for k in range(5):
+        s, c, sn = math.exp(p[k, 2]), math.cos(p[k, 3]), math.sin(p[k, 3])
+        for y in range(20):
+            for x in range(24):
+                dx, dy = x - p[k, 0], y - p[k, 1]
+                U = ((c * dx + sn * dy) / s + 1) / 2 * 31
+                V = ((-sn * dx + c * dy) / s + 1) / 2 * 31
+                if -1 <= math.floor(U) <= 31 and -1 <= math.floor(V) <= 31:
+                    cnt += 1
+    assert n == cnt and n > 0
+
+
+# ------------------------------------------------------------------------------------------
+# Optimiser pieces
+# ------------------------------------------------------------------------------------------
+def test_adam_matches_torch_optim():
+    g = np.random.default_rng(0)
+    theta = g.standard_normal((50, 8))
+    opt = oracle.Adam(theta.shape, lr=1e-2)
+    tt = torch.tensor(theta.copy(), requires_grad=True)
+    topt = torch.optim.Adam([tt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(25):
+        grad = g.standard_normal(theta.shape) * (0.1 + step)
+        theta = opt.step(theta, grad)
+        topt.zero_grad()
+        tt.grad = torch.tensor(grad)
+        topt.step()
+    assert np.max(np.abs(theta - tt.detach().numpy())) < 1e-12
+
+
+def test_mse_gradient():
+    g = np.random.default_rng(1)
+    a, b = g.uniform(0, 1, (3, 5, 7)), g.uniform(0, 1, (3, 5, 7))
+    loss, grad = oracle.mse(a, b)
+    ta = torch.tensor(a, requires_grad=True)
+    tl = F.mse_loss(ta, torch.tensor(b))
+    tl.backward()
+    assert abs(loss - tl.item()) < 1e-15
+    assert np.max(np.abs(grad - ta.grad.numpy())) < 1e-15
