@@ -1,0 +1,154 @@
+/*
+ * diffbmp.h -- C ABI of the MI355X (gfx950) differentiable bitmap-primitive rasteriser.
+ *
+ * The operation is DiffBMP's renderer (arXiv 2602.22625, Sec. 3.1): N bitmap primitives, each
+ * with position (x, y), scale s, rotation theta, opacity logit nu and colour logits c in R^3,
+ * are mapped onto an H x W canvas by the inverse affine map of Eq. (1), sampled bilinearly at
+ * the bitmap coordinates of Eq. (2) (Supp. Eqs. S1-S3), given opacity
+ *     alpha_k = alpha_max * sigmoid(nu_k) * M_k(x, y)                         (Eq. 3)
+ * and composited front to back with Porter-Duff over (Eqs. 4-5), index 0 in front:
+ *     T_0 = 1,  T_{k+1} = T_k (1 - alpha_k),
+ *     I = sum_k T_k alpha_k sigmoid(c_k) + T_N b,   A = 1 - T_N.
+ * The background b (a colour, or one colour per pixel) is the Eq. (8) canvas term; A is the
+ * alpha channel I_alpha of Supp. Alg. 1. The backward returns dL/dparams by the chain rule of
+ * Eq. (7) and Supp. Eqs. (S4)-(S5).
+ *
+ * Conventions shared by every call:
+ *   - params: device float32 [N, 8] row-major, columns x, y, log_s, theta, nu, c_r, c_g, c_b.
+ *     x, y in pixels with pixel (px, py) at canvas point (px, py) (origin top-left, y down);
+ *     s = exp(log_s) is the half-extent in pixels (Eq. 1 divides by s); theta in radians.
+ *   - atlas_idx: device int32 [N], the bitmap of each primitive, in [0, B).
+ *   - atlas: device [B, Hb, Wb] row-major, float32 or bfloat16 (DBMP_F32 / DBMP_BF16), values
+ *     are template masks, normally in [0, 1]; Hb, Wb >= 2. Texels outside a bitmap read as 0.
+ *   - images are planar float32 [3, H, W]; alpha maps float32 [H, W].
+ *   - every device pointer is owned by the caller and must stay valid (and unchanged) until the
+ *     work queued on `stream` has finished; the library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Calls only enqueue work and
+ *     return; none synchronises the host unless its comment says so.
+ *   - return value: DBMP_OK or a negative dbmp_status. Argument errors are detected on the host
+ *     and reported before anything is enqueued. Errors found on the device (an atlas index out
+ *     of range, a non-finite parameter or texel, a full pair buffer) raise a flag in the context
+ *     and are reported by dbmp_check(); the offending primitive is skipped, never read out of
+ *     bounds. No exception ever crosses this interface.
+ */
+#ifndef DIFFBMP_H
+#define DIFFBMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dbmp_ctx dbmp_ctx;
+typedef void *dbmp_stream; /* hipStream_t */
+
+typedef enum {
+    DBMP_OK = 0,
+    DBMP_EINVAL = -1,     /* bad argument (host check) or atlas index out of range (device) */
+    DBMP_ENOMEM = -2,     /* device allocation failed */
+    DBMP_EHIP = -3,       /* a HIP runtime call failed; dbmp_last_error() names it */
+    DBMP_EOVERFLOW = -4,  /* more (tile, primitive) pairs than the pair buffer holds */
+    DBMP_ESTATE = -5,     /* backward without a matching forward on this context */
+    DBMP_ENONFINITE = -6  /* a parameter or atlas texel is NaN or infinite */
+} dbmp_status;
+
+typedef enum { DBMP_F32 = 0, DBMP_BF16 = 1 } dbmp_dtype;
+
+/* Creates a context on HIP device `device`. The context owns the workspace (per-primitive
+ * records, tile lists, the padded atlas and the per-pixel state the backward needs) and grows
+ * it on demand. `pair_capacity` is the initial size of the (tile, primitive) pair buffer in
+ * entries (0 = a default of 2^20). Synchronous. */
+int dbmp_create(dbmp_ctx **out, int device, long long pair_capacity);
+
+/* Releases the context and its workspace. Synchronises the device first. */
+int dbmp_destroy(dbmp_ctx *ctx);
+
+/* Grows the pair buffer to at least `pair_capacity` entries (never shrinks). Synchronous. Use
+ * after dbmp_check() returned DBMP_EOVERFLOW, with dbmp_pair_count() as the size. */
+int dbmp_reserve(dbmp_ctx *ctx, long long pair_capacity);
+
+/*
+ * Forward render of one image (Eqs. 1-5 with background), Sec. 3.1.1.
+ *   params, atlas_idx, N      primitives (see conventions); N >= 0 (N = 0 gives I = b, A = 0).
+ *   atlas, B, Hb, Wb, dtype   bitmap templates.
+ *   H, W                      canvas size, >= 1.
+ *   bg                        device float32: 3 values, or [3, H, W] when bg_per_pixel != 0.
+ *   alpha_max                 in (0, 1] (Eq. 3).
+ *   tile                      screen tile edge in pixels: 8, 16 or 32.
+ *   image                     out, device float32 [3, H, W].
+ *   alpha                     out, device float32 [H, W], A = 1 - T_N; may be NULL.
+ * The context keeps what dbmp_render_backward needs (no per-layer state: the backward
+ * recomputes transmittance per tile); params, atlas and bg must stay unchanged until then.
+ */
+int dbmp_render(dbmp_ctx *ctx, dbmp_stream stream, const float *params, const int32_t *atlas_idx,
+                int N, const void *atlas, int B, int Hb, int Wb, int atlas_dtype, int H, int W,
+                const float *bg, int bg_per_pixel, float alpha_max, int tile, float *image,
+                float *alpha);
+
+/*
+ * Backward of the last dbmp_render / dbmp_render_batched on this context (Eq. 7, Supp. S4-S5).
+ *   dL_dimage   device float32 [3, H, W] (batched: the concatenated layout of the forward).
+ *   dL_dalpha   device float32 [H, W] or NULL (no loss on A).
+ *   dL_dparams  out, device float32 [N, 8], overwritten (columns as in params; the scale
+ *               column is dL/dlog_s).
+ * Returns DBMP_ESTATE if no forward has run on this context.
+ */
+int dbmp_render_backward(dbmp_ctx *ctx, dbmp_stream stream, const float *dL_dimage,
+                         const float *dL_dalpha, float *dL_dparams);
+
+/*
+ * Batched forward: n_images independent images rendered by one persistent launch per stage.
+ * Image i has desc[i] = {H, W, N, prim_offset, pixel_offset}: its primitives are rows
+ * [prim_offset, prim_offset + N) of params / atlas_idx, its image occupies
+ * image[3 * pixel_offset + c * H * W + y * W + x] and its alpha alpha[pixel_offset + y * W + x].
+ * bg: 3 floats per image ([n_images, 3]). All images share the atlas, alpha_max and tile size.
+ * `descs` is a HOST array; it is copied into the context before this call returns.
+ */
+typedef struct {
+    int32_t H, W, N, reserved;
+    int64_t prim_offset;
+    int64_t pixel_offset;
+} dbmp_image_desc;
+
+int dbmp_render_batched(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
+                        const dbmp_image_desc *descs, const float *params,
+                        const int32_t *atlas_idx, const void *atlas, int B, int Hb, int Wb,
+                        int atlas_dtype, const float *bg, float alpha_max, int tile,
+                        float *image, float *alpha);
+
+/* Synchronises `stream` and reports device-side flags of the last forward/backward:
+ * DBMP_EOVERFLOW, DBMP_EINVAL (atlas index out of range), DBMP_ENONFINITE, or DBMP_OK.
+ * Clears nothing: the next forward resets the flags. */
+int dbmp_check(dbmp_ctx *ctx, dbmp_stream stream);
+
+/* Number of (tile, primitive) pairs of the last forward. Synchronises `stream`. */
+long long dbmp_pair_count(dbmp_ctx *ctx, dbmp_stream stream);
+
+/* Message of the last error on this context ("" if none). Valid until the next call. */
+const char *dbmp_last_error(const dbmp_ctx *ctx);
+
+/*
+ * Mean-squared-error gradient over n values (the `mse` loss of the paper's configuration, Supp.
+ * Table S1): grad[i] = 2 (image[i] - target[i]) / n. If loss_sum != NULL, sum_i (image[i] -
+ * target[i])^2 is ADDED to *loss_sum (device float32; the caller zeroes it).
+ */
+int dbmp_mse_grad(dbmp_stream stream, const float *image, const float *target, long long n,
+                  float *grad, float *loss_sum);
+
+/*
+ * One Adam step (Kingma & Ba, Algorithm 1; the optimiser of Supp. Table S1 with a flat rate) on
+ * n float32 values in place: m, v are the moment buffers (zero before the first step), *step is
+ * a device int32 counter of steps already taken (zero before the first step); this call uses
+ * t = *step + 1 for the bias correction and then increments *step on the device, so the call
+ * can be replayed from a captured graph.
+ */
+int dbmp_adam_step(dbmp_stream stream, float *params, const float *grad, float *m, float *v,
+                   long long n, float lr, float beta1, float beta2, float eps, int32_t *step);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIFFBMP_H */

@@ -1,0 +1,153 @@
+"""ctypes binding of libdiffbmp.so (include/diffbmp.h). Argument marshalling only: every
+function here forwards to the C function of the same name; tensors are passed as device
+pointers, streams as raw hipStream_t handles. There is no fallback: if the library is missing
+the import of a function raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiffbmp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "diffbmp.h")
+
+DBMP_OK, DBMP_EINVAL, DBMP_ENOMEM, DBMP_EHIP, DBMP_EOVERFLOW, DBMP_ESTATE, DBMP_ENONFINITE = \
+    0, -1, -2, -3, -4, -5, -6
+DBMP_F32, DBMP_BF16 = 0, 1
+STATUS_NAMES = {0: "DBMP_OK", -1: "DBMP_EINVAL", -2: "DBMP_ENOMEM", -3: "DBMP_EHIP",
+                -4: "DBMP_EOVERFLOW", -5: "DBMP_ESTATE", -6: "DBMP_ENONFINITE"}
+
+
+class DbmpError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class ImageDesc(ctypes.Structure):
+    """dbmp_image_desc"""
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("prim_offset", ctypes.c_int64),
+                ("pixel_offset", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libdiffbmp.so. torch is imported first so that the library binds to the HIP
+    runtime torch already loaded (both carry the soname libamdhip64.so.7)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdiffbmp.so is not built: run `python -m paper_2602_22625_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, LL, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_float
+    sig = {
+        "dbmp_create": ([ctypes.POINTER(P), I, LL], I),
+        "dbmp_destroy": ([P], I),
+        "dbmp_reserve": ([P, LL], I),
+        "dbmp_render": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P], I),
+        "dbmp_render_backward": ([P, P, P, P, P], I),
+        "dbmp_render_batched": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P], I),
+        "dbmp_check": ([P, P], I),
+        "dbmp_pair_count": ([P, P], LL),
+        "dbmp_last_error": ([P], ctypes.c_char_p),
+        "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
+        "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def ptr(x):
+    """Device pointer of a tensor (or None / int passthrough)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _chk(ctx, rc):
+    if rc != DBMP_OK:
+        msg = load().dbmp_last_error(ctx).decode() if ctx else ""
+        raise DbmpError(rc, msg)
+    return rc
+
+
+# ------------------------------------------------------------------------------------------
+# Same-name wrappers
+# ------------------------------------------------------------------------------------------
+def dbmp_create(device=0, pair_capacity=0):
+    h = ctypes.c_void_p()
+    _chk(None, load().dbmp_create(ctypes.byref(h), int(device), int(pair_capacity)))
+    return h.value
+
+
+def dbmp_destroy(ctx):
+    return _chk(None, load().dbmp_destroy(ctx))
+
+
+def dbmp_reserve(ctx, pair_capacity):
+    return _chk(ctx, load().dbmp_reserve(ctx, int(pair_capacity)))
+
+
+def dbmp_render(ctx, stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dtype, H, W, bg,
+                bg_per_pixel, alpha_max, tile, image, alpha):
+    return _chk(ctx, load().dbmp_render(ctx, stream, ptr(params), ptr(atlas_idx), int(N),
+                                        ptr(atlas), int(B), int(Hb), int(Wb), int(atlas_dtype),
+                                        int(H), int(W), ptr(bg), int(bg_per_pixel),
+                                        float(alpha_max), int(tile), ptr(image), ptr(alpha)))
+
+
+def dbmp_render_backward(ctx, stream, dL_dimage, dL_dalpha, dL_dparams):
+    return _chk(ctx, load().dbmp_render_backward(ctx, stream, ptr(dL_dimage), ptr(dL_dalpha),
+                                                 ptr(dL_dparams)))
+
+
+def dbmp_render_batched(ctx, stream, descs, params, atlas_idx, atlas, B, Hb, Wb, atlas_dtype,
+                        bg, alpha_max, tile, image, alpha):
+    arr = (ImageDesc * len(descs))(*descs)
+    return _chk(ctx, load().dbmp_render_batched(ctx, stream, len(descs), arr, ptr(params),
+                                                ptr(atlas_idx), ptr(atlas), int(B), int(Hb),
+                                                int(Wb), int(atlas_dtype), ptr(bg),
+                                                float(alpha_max), int(tile), ptr(image),
+                                                ptr(alpha)))
+
+
+def dbmp_check(ctx, stream):
+    """Returns the status code (does not raise)."""
+    return load().dbmp_check(ctx, stream)
+
+
+def dbmp_pair_count(ctx, stream):
+    return int(load().dbmp_pair_count(ctx, stream))
+
+
+def dbmp_last_error(ctx):
+    return load().dbmp_last_error(ctx).decode()
+
+
+def dbmp_mse_grad(stream, image, target, n, grad, loss_sum):
+    return _chk(None, load().dbmp_mse_grad(stream, ptr(image), ptr(target), int(n), ptr(grad),
+                                           ptr(loss_sum)))
+
+
+def dbmp_adam_step(stream, params, grad, m, v, n, lr, beta1, beta2, eps, step):
+    return _chk(None, load().dbmp_adam_step(stream, ptr(params), ptr(grad), ptr(m), ptr(v),
+                                            int(n), float(lr), float(beta1), float(beta2),
+                                            float(eps), ptr(step)))

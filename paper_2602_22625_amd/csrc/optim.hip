@@ -1,0 +1,92 @@
+// Loss gradient and optimiser step (the `mse` loss and Adam optimiser of the paper's
+// configuration, Supp. Table S1; here with a flat learning rate). Both are HBM-bound streams.
+#include "dbmp_internal.h"
+#include "diffbmp.h"
+
+namespace dbmp {
+
+__global__ void __launch_bounds__(256)
+k_mse_grad(const float4 *__restrict__ img, const float4 *__restrict__ tgt, long long n4,
+           const float *__restrict__ img1, const float *__restrict__ tgt1, long long n,
+           float *__restrict__ grad, float scale, float *__restrict__ loss_sum)
+{
+    float acc = 0.f;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    float4 *g4 = (float4 *)grad;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 a = img[i], b = tgt[i];
+        const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+        g4[i] = make_float4(scale * d.x, scale * d.y, scale * d.z, scale * d.w);
+        acc = fmaf(d.x, d.x, acc); acc = fmaf(d.y, d.y, acc);
+        acc = fmaf(d.z, d.z, acc); acc = fmaf(d.w, d.w, acc);
+    }
+    for (long long i = 4 * n4 + (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride) {
+        const float d = img1[i] - tgt1[i];
+        grad[i] = scale * d;
+        acc = fmaf(d, d, acc);
+    }
+    if (!loss_sum) return;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    __shared__ float ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss_sum, ws[0] + ws[1] + ws[2] + ws[3]);
+}
+
+__global__ void __launch_bounds__(256)
+k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+       float *__restrict__ v, long long n, float lr, float b1, float b2, float eps,
+       const int *__restrict__ step)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = *step + 1;
+    // bias corrections 1 - beta^t, evaluated in float64 once per thread (cheap, exact enough)
+    const float c1 = (float)(1.0 - pow((double)b1, (double)t));
+    const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float mhat = mi / c1, vhat = vi / c2;
+    p[i] = p[i] - lr * mhat / (sqrtf(vhat) + eps);
+}
+
+__global__ void k_step_inc(int *__restrict__ step) { *step += 1; }
+
+}  // namespace dbmp
+
+using namespace dbmp;
+
+extern "C" int dbmp_mse_grad(dbmp_stream stream, const float *image, const float *target,
+                             long long n, float *grad, float *loss_sum)
+{
+    if (n < 0 || (n > 0 && (!image || !target || !grad))) return DBMP_EINVAL;
+    if (n == 0) return DBMP_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool aligned = (((uintptr_t)image | (uintptr_t)target | (uintptr_t)grad) & 15) == 0;
+    const long long n4 = aligned ? n / 4 : 0;
+    long long blocks = (n + 1023) / 1024;
+    if (blocks > 4096) blocks = 4096;
+    k_mse_grad<<<(unsigned)blocks, 256, 0, st>>>((const float4 *)image, (const float4 *)target,
+                                                 n4, image, target, n, grad, 2.0f / (float)n,
+                                                 loss_sum);
+    return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP;
+}
+
+extern "C" int dbmp_adam_step(dbmp_stream stream, float *params, const float *grad, float *m,
+                              float *v, long long n, float lr, float beta1, float beta2,
+                              float eps, int32_t *step)
+{
+    if (n < 0 || !step || (n > 0 && (!params || !grad || !m || !v))) return DBMP_EINVAL;
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return DBMP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (n > 0)
+        k_adam<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(params, grad, m, v, n, lr, beta1,
+                                                            beta2, eps, step);
+    k_step_inc<<<1, 1, 0, st>>>(step);
+    return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP;
+}

@@ -1,0 +1,182 @@
+"""PyTorch-facing layer over the C ABI: a Renderer (owns one dbmp context) and RenderFn, the
+torch.autograd.Function whose backward is dbmp_render_backward.
+
+PyTorch supplies device memory and the stream only; every step of the forward and backward runs
+in the library's HIP kernels. The forward keeps no per-layer state: the context holds the tile
+lists and O(1) values per pixel, and the backward recomputes transmittance per tile.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import capi
+
+
+def _dtype_code(atlas: torch.Tensor) -> int:
+    if atlas.dtype == torch.float32:
+        return capi.DBMP_F32
+    if atlas.dtype == torch.bfloat16:
+        return capi.DBMP_BF16
+    raise TypeError("atlas must be float32 or bfloat16, got %s" % atlas.dtype)
+
+
+def _need(t, name, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+class Renderer:
+    """One dbmp context. `check=True` synchronises after each forward to detect a full pair
+    buffer, grows it and renders again; `check=False` keeps every call asynchronous (for graph
+    capture) and leaves overflow to an explicit `check()`."""
+
+    def __init__(self, device=None, pair_capacity: int = 0, check: bool = True):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        self.ctx = capi.dbmp_create(dev.index, pair_capacity)
+        self.check_each = check
+        self.generation = 0
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                capi.dbmp_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    # -- forward -----------------------------------------------------------------------------
+    def render(self, params, atlas_idx, atlas, H, W, bg=None, alpha_max=1.0, tile=16,
+               image=None, alpha=None, with_alpha=True):
+        _need(params, "params", torch.float32)
+        N = params.shape[0]
+        if params.dim() != 2 or params.shape[1] != 8:
+            raise ValueError("params must be [N, 8]")
+        _need(atlas_idx, "atlas_idx", torch.int32, (N,))
+        if atlas.dim() == 2:
+            atlas = atlas[None]
+        _need(atlas, "atlas")
+        B, Hb, Wb = atlas.shape
+        if bg is None:
+            bg = torch.ones(3, device=params.device, dtype=torch.float32)
+        _need(bg, "bg", torch.float32)
+        if bg.numel() == 3:
+            bg_pp = 0
+        elif tuple(bg.shape) == (3, H, W):
+            bg_pp = 1
+        else:
+            raise ValueError("bg must have 3 values or shape [3, H, W]")
+        if image is None:
+            image = torch.empty(3, H, W, device=params.device, dtype=torch.float32)
+        _need(image, "image", torch.float32, (3, H, W))
+        if alpha is None and with_alpha:
+            alpha = torch.empty(H, W, device=params.device, dtype=torch.float32)
+        if alpha is not None:
+            _need(alpha, "alpha", torch.float32, (H, W))
+        st = capi.stream_handle()
+        args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, _dtype_code(atlas), H, W,
+                bg, bg_pp, alpha_max, tile, image, alpha)
+        capi.dbmp_render(*args)
+        if self.check_each:
+            rc = capi.dbmp_check(self.ctx, st)
+            if rc == capi.DBMP_EOVERFLOW:
+                need = capi.dbmp_pair_count(self.ctx, st)
+                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 4096)
+                capi.dbmp_render(*args)
+                rc = capi.dbmp_check(self.ctx, st)
+            if rc != capi.DBMP_OK:
+                raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
+        self.generation += 1
+        return image, alpha
+
+    def render_batched(self, descs, params, atlas_idx, atlas, bg, alpha_max=1.0, tile=16,
+                       image=None, alpha=None):
+        """descs: list of (H, W, N, prim_offset, pixel_offset). bg: [n_images, 3]."""
+        _need(params, "params", torch.float32)
+        _need(atlas_idx, "atlas_idx", torch.int32)
+        _need(atlas, "atlas")
+        _need(bg, "bg", torch.float32, (len(descs), 3))
+        B, Hb, Wb = atlas.shape
+        npix = max(int(d[4]) + int(d[0]) * int(d[1]) for d in descs)
+        if image is None:
+            image = torch.empty(3 * npix, device=params.device, dtype=torch.float32)
+        if alpha is None:
+            alpha = torch.empty(npix, device=params.device, dtype=torch.float32)
+        cd = [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))
+              for (h, w, n, po, xo) in descs]
+        st = capi.stream_handle()
+        args = (self.ctx, st, cd, params, atlas_idx, atlas, B, Hb, Wb, _dtype_code(atlas), bg,
+                alpha_max, tile, image, alpha)
+        capi.dbmp_render_batched(*args)
+        if self.check_each:
+            rc = capi.dbmp_check(self.ctx, st)
+            if rc == capi.DBMP_EOVERFLOW:
+                need = capi.dbmp_pair_count(self.ctx, st)
+                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 4096)
+                capi.dbmp_render_batched(*args)
+                rc = capi.dbmp_check(self.ctx, st)
+            if rc != capi.DBMP_OK:
+                raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
+        self.generation += 1
+        return image, alpha
+
+    # -- backward ----------------------------------------------------------------------------
+    def backward(self, dL_dimage, dL_dalpha=None, n_params=None, out=None):
+        _need(dL_dimage, "dL_dimage", torch.float32)
+        if dL_dalpha is not None:
+            _need(dL_dalpha, "dL_dalpha", torch.float32)
+        if out is None:
+            out = torch.empty(n_params, 8, device=dL_dimage.device, dtype=torch.float32)
+        capi.dbmp_render_backward(self.ctx, capi.stream_handle(), dL_dimage, dL_dalpha, out)
+        return out
+
+    def check(self):
+        rc = capi.dbmp_check(self.ctx, capi.stream_handle())
+        if rc != capi.DBMP_OK:
+            raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
+
+    def pair_count(self):
+        return capi.dbmp_pair_count(self.ctx, capi.stream_handle())
+
+
+class RenderFn(torch.autograd.Function):
+    """(image, alpha) = RenderFn.apply(params, renderer, atlas_idx, atlas, H, W, bg, alpha_max,
+    tile). Differentiable in params only. The backward re-runs the forward on the renderer if
+    another forward has used it since (its saved per-tile state belongs to the last one)."""
+
+    @staticmethod
+    def forward(fctx, params, renderer, atlas_idx, atlas, H, W, bg, alpha_max, tile):
+        fctx.set_materialize_grads(False)
+        p = params.detach()
+        image, alpha = renderer.render(p, atlas_idx, atlas, H, W, bg, alpha_max, tile)
+        fctx.renderer = renderer
+        fctx.generation = renderer.generation
+        fctx.cfg = (H, W, alpha_max, tile)
+        fctx.save_for_backward(p, atlas_idx, atlas, bg)
+        return image, alpha
+
+    @staticmethod
+    def backward(fctx, g_image, g_alpha):
+        p, atlas_idx, atlas, bg = fctx.saved_tensors
+        r = fctx.renderer
+        H, W, alpha_max, tile = fctx.cfg
+        if r.generation != fctx.generation:
+            r.render(p, atlas_idx, atlas, H, W, bg, alpha_max, tile)
+        if g_image is None:
+            g_image = torch.zeros(3, H, W, device=p.device, dtype=torch.float32)
+        d = r.backward(g_image.contiguous(), None if g_alpha is None else g_alpha.contiguous(),
+                       n_params=p.shape[0])
+        return d, None, None, None, None, None, None, None, None
+
+
+def render(params, renderer, atlas_idx, atlas, H, W, bg=None, alpha_max=1.0, tile=16):
+    if bg is None:
+        bg = torch.ones(3, device=params.device, dtype=torch.float32)
+    return RenderFn.apply(params, renderer, atlas_idx, atlas, H, W, bg, alpha_max, tile)

@@ -1,0 +1,45 @@
+"""The C-ABI library loads on a host without a GPU, exports every function include/diffbmp.h
+declares, and rejects bad arguments on the host before touching the device."""
+import ctypes
+import re
+
+import pytest
+
+from paper_2602_22625_amd import capi
+
+
+def header_functions():
+    src = open(capi.HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dbmp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for n in ["dbmp_create", "dbmp_destroy", "dbmp_render", "dbmp_render_backward",
+              "dbmp_render_batched", "dbmp_check", "dbmp_last_error", "dbmp_mse_grad",
+              "dbmp_adam_step", "dbmp_reserve", "dbmp_pair_count"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = capi.load()
+    for n in header_functions():
+        assert hasattr(lib, n), n
+
+
+def test_host_argument_checks_need_no_device():
+    lib = capi.load()
+    assert lib.dbmp_render(None, None, None, None, 0, None, 1, 2, 2, 0, 4, 4, None, 0, 1.0, 16,
+                           None, None) == capi.DBMP_EINVAL
+    assert lib.dbmp_render_backward(None, None, None, None, None) == capi.DBMP_EINVAL
+    assert lib.dbmp_mse_grad(None, None, None, -1, None, None) == capi.DBMP_EINVAL
+    assert lib.dbmp_mse_grad(None, None, None, 0, None, None) == capi.DBMP_OK
+    assert lib.dbmp_adam_step(None, None, None, None, None, 4, 1e-2, 0.9, 0.999, 1e-8,
+                              None) == capi.DBMP_EINVAL
+    assert lib.dbmp_check(None, None) == capi.DBMP_EINVAL
+    assert lib.dbmp_reserve(None, 10) == capi.DBMP_EINVAL
+    assert lib.dbmp_destroy(None) == capi.DBMP_EINVAL
+    assert lib.dbmp_last_error(None) == b"null context"
+    h = ctypes.c_void_p()
+    assert lib.dbmp_create(ctypes.byref(h), 0, -5) == capi.DBMP_EINVAL

@@ -1,0 +1,348 @@
+"""GPU parity: the HIP rasteriser (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (fixed by the requirement on this path):
+  images     max|I_gpu - I_ref| / max|I_ref|                          <= 1e-5
+  gradients  per parameter block {xy, log_s, theta, nu, colour}:
+             max|g_gpu - g_ref| / max|g_ref|  and  ||g_gpu - g_ref||_2 / ||g_ref||_2  <= 1e-4
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_22625_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-4
+BLOCKS = {"xy": [0, 1], "log_s": [2], "theta": [3], "nu": [4], "colour": [5, 6, 7]}
+
+
+def img_err(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    return float(np.max(np.abs(gpu - ref)) / max(np.max(np.abs(ref)), 1e-12))
+
+
+def grad_errs(gpu, ref):
+    out = {}
+    for k, cols in BLOCKS.items():
+        a = np.asarray(gpu, dtype=np.float64)[:, cols]
+        b = ref[:, cols]
+        inf = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30)
+        l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        out[k] = (float(inf), float(l2))
+    return out
+
+
+def assert_grads(gpu, ref, tol=GRAD_TOL):
+    errs = grad_errs(gpu, ref)
+    bad = {k: v for k, v in errs.items() if v[0] > tol or v[1] > tol}
+    assert not bad, errs
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2602_22625_amd.render import Renderer
+    return Renderer()
+
+
+def to_dev(d, atlas_bf16=False):
+    dev = torch.device("cuda")
+    p = torch.tensor(d["params"], device=dev)
+    idx = torch.tensor(d["idx"], device=dev)
+    if atlas_bf16:
+        a = torch.tensor(d["atlas_bf16"].view(np.int16), device=dev).view(torch.bfloat16)
+    else:
+        a = torch.tensor(d["atlas"], device=dev)
+    return p, idx, a
+
+
+def gpu_render(R, p, idx, a, H, W, bg, alpha_max=1.0, tile=16):
+    bg_t = torch.tensor(np.asarray(bg, dtype=np.float32), device="cuda")
+    img, alp = R.render(p, idx, a, H, W, bg_t, alpha_max, tile)
+    torch.cuda.synchronize()
+    return img, alp, bg_t
+
+
+def gpu_grad(R, gI, gA, N):
+    gI_t = torch.tensor(gI, dtype=torch.float32, device="cuda")
+    gA_t = None if gA is None else torch.tensor(gA, dtype=torch.float32, device="cuda")
+    out = R.backward(gI_t, gA_t, n_params=N)
+    R.check()
+    return out.cpu().numpy()
+
+
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_c0_forward_backward(R, tile):
+    d = synth.make_workload("c0")
+    H = W = 128
+    p, idx, a = to_dev(d)
+    img, alp, _ = gpu_render(R, p, idx, a, H, W, (1, 1, 1), tile=tile)
+    ref, refA = oracle.render(d["params"], d["idx"], d["atlas"], H, W)
+    assert img_err(img.cpu(), ref) <= IMG_TOL
+    assert img_err(alp.cpu(), refA) <= IMG_TOL
+    g = np.random.default_rng(1).standard_normal((3, H, W))
+    gA = np.random.default_rng(2).standard_normal((H, W))
+    gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], H, W, g, gA)
+    assert_grads(gpu_grad(R, g, gA, 64), gref)
+
+
+def test_images_bitwise_identical_across_tile_sizes(R):
+    d = synth.make_workload("c1")
+    p, idx, a = to_dev(d)
+    outs = []
+    for tile in (8, 16, 32):
+        img, alp, _ = gpu_render(R, p, idx, a, 512, 512, (1, 1, 1), tile=tile)
+        outs.append((img.cpu().numpy().copy(), alp.cpu().numpy().copy()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_c1_crop_forward_backward(R):
+    """Full 512x512 / 4096-primitive GPU render; oracle on a 160x144 window (many tiles, ragged
+    window edges) with the loss gradient restricted to that window."""
+    d = synth.make_workload("c1")
+    H = W = 512
+    p, idx, a = to_dev(d)
+    img, alp, _ = gpu_render(R, p, idx, a, H, W, (1, 1, 1))
+    crop = (203, 77, 160, 144)
+    x0, y0, w, h = crop
+    ref, refA = oracle.render(d["params"], d["idx"], d["atlas"], H, W, crop=crop)
+    assert img_err(img.cpu().numpy()[:, y0:y0 + h, x0:x0 + w], ref) <= IMG_TOL
+    assert img_err(alp.cpu().numpy()[y0:y0 + h, x0:x0 + w], refA) <= IMG_TOL
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((3, h, w))
+    gA = rng.standard_normal((h, w))
+    gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], H, W, g, gA, crop=crop)
+    G = np.zeros((3, H, W)); G[:, y0:y0 + h, x0:x0 + w] = g
+    GA = np.zeros((H, W)); GA[y0:y0 + h, x0:x0 + w] = gA
+    ggpu = gpu_grad(R, G, GA, d["params"].shape[0])
+    touched = np.abs(gref).sum(axis=1) > 0
+    assert touched.sum() > 100
+    assert_grads(ggpu, gref)
+    assert np.all(ggpu[~touched] == 0.0)  # primitives outside the window get exactly zero
+
+
+def test_ragged_bf16_per_pixel_background(R):
+    """A canvas that is not a multiple of the tile, bf16 atlas, per-pixel background,
+    alpha_max < 1."""
+    g = np.random.default_rng(5)
+    H, W, N = 77, 101, 300
+    atlas = synth.make_atlas("ss64x16")
+    bits = synth.f32_to_bf16_bits(atlas)
+    atl = synth.bf16_bits_to_f32(bits)
+    params, idx = synth.init_params(N, H, W, math.log(9.0), 0.5, atlas.shape[0], 77)
+    bg = g.uniform(0, 1, (3, H, W)).astype(np.float32)
+    d = dict(params=params, idx=idx, atlas=atl, atlas_bf16=bits)
+    p, i_t, a = to_dev(d, atlas_bf16=True)
+    for tile in (8, 16, 32):
+        img, alp, _ = gpu_render(R, p, i_t, a, H, W, bg, alpha_max=0.8, tile=tile)
+        ref, refA = oracle.render(params, idx, atl, H, W, bg=bg, alpha_max=0.8)
+        assert img_err(img.cpu(), ref) <= IMG_TOL
+        assert img_err(alp.cpu(), refA) <= IMG_TOL
+        gI = g.standard_normal((3, H, W))
+        gref = oracle.render_backward(params, idx, atl, H, W, gI, None, bg=bg, alpha_max=0.8)
+        assert_grads(gpu_grad(R, gI, None, N), gref)
+
+
+def test_c2_full_size_sampled_windows(R):
+    """2048x2048, 65,536 primitives, bf16 atlas, 16x16 tiles: the oracle checks two windows of
+    the full-size GPU render, and the gradient of a window-restricted loss."""
+    d = synth.make_workload("c2")
+    H = W = 2048
+    p, idx, a = to_dev(d, atlas_bf16=True)
+    img, alp, _ = gpu_render(R, p, idx, a, H, W, (1, 1, 1), tile=16)
+    imgn, alpn = img.cpu().numpy(), alp.cpu().numpy()
+    for crop in [(1000, 1000, 40, 40), (2017, 3, 31, 29)]:
+        x0, y0, w, h = crop
+        ref, refA = oracle.render(d["params"], d["idx"], d["atlas"], H, W, crop=crop)
+        assert img_err(imgn[:, y0:y0 + h, x0:x0 + w], ref) <= IMG_TOL
+        assert img_err(alpn[y0:y0 + h, x0:x0 + w], refA) <= IMG_TOL
+    crop = (1000, 1000, 40, 40)
+    x0, y0, w, h = crop
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal((3, h, w))
+    G = np.zeros((3, H, W), dtype=np.float32); G[:, y0:y0 + h, x0:x0 + w] = g
+    gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], H, W, g, None, crop=crop)
+    ggpu = gpu_grad(R, G, None, d["params"].shape[0])
+    assert_grads(ggpu, gref)
+
+
+# ------------------------------------------------------------------------------------------
+# Edge cases
+# ------------------------------------------------------------------------------------------
+def test_no_primitives_gives_background(R):
+    a = torch.tensor(synth.soft_disk(32)[None], device="cuda")
+    p = torch.zeros(0, 8, device="cuda")
+    idx = torch.zeros(0, dtype=torch.int32, device="cuda")
+    img, alp, _ = gpu_render(R, p, idx, a, 37, 45, (0.25, 0.5, 0.75))
+    assert torch.all(img[0] == 0.25) and torch.all(img[1] == 0.5) and torch.all(img[2] == 0.75)
+    assert torch.all(alp == 0)
+    out = R.backward(torch.ones(3, 37, 45, device="cuda"), None, n_params=0)
+    assert out.numel() == 0
+
+
+def test_off_canvas_and_zero_opacity_primitives(R):
+    d = synth.make_workload("c0")
+    params = d["params"].copy()
+    params[3, 0] = -500.0        # far off canvas
+    params[7, 4] = -1000.0       # sigmoid(nu) == 0
+    p = torch.tensor(params, device="cuda")
+    idx = torch.tensor(d["idx"], device="cuda")
+    a = torch.tensor(d["atlas"], device="cuda")
+    img, alp, _ = gpu_render(R, p, idx, a, 128, 128, (1, 1, 1))
+    ref, _ = oracle.render(params, d["idx"], d["atlas"], 128, 128)
+    assert img_err(img.cpu(), ref) <= IMG_TOL
+    g = np.random.default_rng(4).standard_normal((3, 128, 128))
+    gg = gpu_grad(R, g, None, 64)
+    assert np.all(gg[3] == 0) and np.all(gg[7] == 0)
+    gref = oracle.render_backward(params, d["idx"], d["atlas"], 128, 128, g, None)
+    assert_grads(gg, gref)
+
+
+def test_fully_opaque_layers_and_deep_stacks(R):
+    """alpha = 1 exactly (alpha_max = 1, sigmoid(nu) rounds to 1, solid texels) and 400 layers
+    over one region, so transmittance reaches 0 and drops below every threshold."""
+    H = W = 48
+    g = np.random.default_rng(9)
+    solid = np.ones((1, 16, 16), dtype=np.float32)
+    disk = synth.soft_disk(32)[::2, ::2][None].astype(np.float32)
+    atlas = np.concatenate([solid, disk, np.zeros_like(solid)]).astype(np.float32)
+    N = 400
+    params = np.zeros((N, 8), dtype=np.float32)
+    params[:, 0] = g.uniform(16, 32, N)
+    params[:, 1] = g.uniform(16, 32, N)
+    params[:, 2] = np.log(g.uniform(6, 12, N))
+    params[:, 3] = g.uniform(0, 2 * np.pi, N)
+    params[:, 4] = g.normal(1.0, 2.0, N)
+    params[:, 5:] = g.normal(0, 1, (N, 3))
+    params[::37, 4] = 40.0   # opaque layers (alpha == 1 on the solid bitmap)
+    idx = g.integers(0, 2, N).astype(np.int32)
+    idx[::37] = 0
+    idx[5] = 2               # an all-zero bitmap
+    d = dict(params=params, idx=idx, atlas=atlas)
+    p, i_t, a = to_dev(d)
+    img, alp, _ = gpu_render(R, p, i_t, a, H, W, (0.3, 0.2, 0.1))
+    ref, refA = oracle.render(params, idx, atlas, H, W, bg=(0.3, 0.2, 0.1))
+    assert img_err(img.cpu(), ref) <= IMG_TOL
+    gI = g.standard_normal((3, H, W))
+    gA = g.standard_normal((H, W))
+    gref = oracle.render_backward(params, idx, atlas, H, W, gI, gA, bg=(0.3, 0.2, 0.1))
+    gg = gpu_grad(R, gI, gA, N)
+    assert np.all(np.isfinite(gg))
+    assert_grads(gg, gref)
+
+
+def test_long_tile_lists_all_sort_paths(R):
+    """Tile lists of > 64 and > 2048 entries (register, LDS and global-memory sort paths)."""
+    H = W = 64
+    g = np.random.default_rng(10)
+    atlas = synth.soft_disk(32)[None]
+    N = 3000
+    params = np.zeros((N, 8), dtype=np.float32)
+    params[:, 0] = g.uniform(0, 64, N)
+    params[:, 1] = g.uniform(0, 64, N)
+    params[:, 2] = np.log(g.uniform(8, 30, N))
+    params[:, 3] = g.uniform(0, 6.28, N)
+    params[:, 4] = g.normal(-4, 1, N)
+    params[:, 5:] = g.normal(0, 1, (N, 3))
+    idx = np.zeros(N, dtype=np.int32)
+    d = dict(params=params, idx=idx, atlas=atlas)
+    p, i_t, a = to_dev(d)
+    ref, _ = oracle.render(params, idx, atlas, H, W)
+    for tile in (8, 32):
+        img, _, _ = gpu_render(R, p, i_t, a, H, W, (1, 1, 1), tile=tile)
+        assert img_err(img.cpu(), ref) <= IMG_TOL
+    assert R.pair_count() > 2048
+
+
+def test_device_errors_are_flagged(R):
+    from paper_2602_22625_amd import capi
+    d = synth.make_workload("c0")
+    p, idx, a = to_dev(d)
+    bad = idx.clone()
+    bad[5] = 7  # atlas has one bitmap
+    with pytest.raises(capi.DbmpError) as e:
+        gpu_render(R, p, bad, a, 128, 128, (1, 1, 1))
+    assert e.value.code == capi.DBMP_EINVAL
+    pn = p.clone()
+    pn[3, 2] = float("nan")
+    with pytest.raises(capi.DbmpError) as e:
+        gpu_render(R, pn, idx, a, 128, 128, (1, 1, 1))
+    assert e.value.code == capi.DBMP_ENONFINITE
+    # host-side argument checks
+    bg = torch.ones(3, device="cuda")
+    with pytest.raises(capi.DbmpError):
+        R.render(p, idx, a, 128, 128, bg, 1.5, 16)
+    with pytest.raises(capi.DbmpError):
+        R.render(p, idx, a, 128, 128, bg, 1.0, 12)
+
+
+def test_pair_buffer_overflow_is_reported_then_grown():
+    from paper_2602_22625_amd import capi
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c1")
+    p, idx, a = to_dev(d)
+    small = Renderer(pair_capacity=1000, check=False)
+    bg = torch.ones(3, device="cuda")
+    small.render(p, idx, a, 512, 512, bg, 1.0, 16)
+    assert capi.dbmp_check(small.ctx, capi.stream_handle()) == capi.DBMP_EOVERFLOW
+    need = small.pair_count()
+    assert need > 1000
+    capi.dbmp_reserve(small.ctx, need)
+    img, _ = small.render(p, idx, a, 512, 512, bg, 1.0, 16)
+    small.check()
+    big = Renderer()
+    img2, _ = big.render(p, idx, a, 512, 512, bg, 1.0, 16)
+    torch.cuda.synchronize()
+    assert torch.equal(img, img2)
+
+
+def test_batched_equals_single(R):
+    from paper_2602_22625_amd.render import Renderer
+    g = np.random.default_rng(12)
+    atlas = synth.make_atlas("ss64x16")
+    sizes = [(64, 80, 150), (200, 120, 900), (33, 47, 40), (128, 128, 0), (96, 96, 500)]
+    descs, ps, ids, po, xo = [], [], [], 0, 0
+    for k, (H, W, N) in enumerate(sizes):
+        pr, ix = synth.init_params(N, H, W, math.log(10.0), 0.5, 16, 900 + k)
+        descs.append((H, W, N, po, xo))
+        ps.append(pr); ids.append(ix)
+        po += N + 3   # gaps between images' primitive ranges are allowed
+        ps.append(np.zeros((3, 8), np.float32)); ids.append(np.zeros(3, np.int32))
+        xo += H * W + 5
+    P = torch.tensor(np.concatenate(ps), device="cuda")
+    I = torch.tensor(np.concatenate(ids), device="cuda")
+    A = torch.tensor(atlas, device="cuda")
+    bgs = torch.tensor(g.uniform(0, 1, (len(sizes), 3)).astype(np.float32), device="cuda")
+    Rb = Renderer()
+    img, alp = Rb.render_batched(descs, P, I, A, bgs, 1.0, 16)
+    torch.cuda.synchronize()
+    for k, (H, W, N, p0, x0) in enumerate(descs):
+        si, sa = R.render(P[p0:p0 + N].contiguous(), I[p0:p0 + N].contiguous(), A, H, W,
+                          bgs[k].contiguous(), 1.0, 16)
+        torch.cuda.synchronize()
+        bi = img[3 * x0:3 * x0 + 3 * H * W].view(3, H, W)
+        assert torch.equal(bi, si), k
+        assert torch.equal(alp[x0:x0 + H * W].view(H, W), sa), k
+
+
+def test_autograd_function_matches_oracle(R):
+    from paper_2602_22625_amd.render import render
+    d = synth.make_workload("c0")
+    p = torch.tensor(d["params"], device="cuda", requires_grad=True)
+    idx = torch.tensor(d["idx"], device="cuda")
+    a = torch.tensor(d["atlas"], device="cuda")
+    tgt = torch.tensor(d["target"], device="cuda")
+    img, alp = render(p, R, idx, a, 128, 128)
+    loss = ((img - tgt) ** 2).mean() + 0.5 * alp.mean()
+    loss.backward()
+    ref, refA = oracle.render(d["params"], d["idx"], d["atlas"], 128, 128)
+    _, gI = oracle.mse(ref, d["target"])
+    gA = np.full((128, 128), 0.5 / (128 * 128))
+    gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], 128, 128, gI, gA)
+    assert_grads(p.grad.cpu().numpy(), gref)
