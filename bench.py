@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the differentiable bitmap-primitive rasteriser on one MI355X.
+
+A step is one plain Adam iteration on the 512x512 workload (4,096 primitives, 16 star/stroke
+bitmaps of 64x64 fp32, 16x16 tiles): per-primitive setup and binning, forward compositing, MSE
+gradient, backward, Adam, replayed from a captured HIP graph. Inputs are resident in HBM before
+the timed region. The value is primitive-pixel evaluations per second over forward + backward:
+(pixel, primitive) pairs evaluated by the timed steps (counted on the device, one popcount per
+wave and primitive; the count is pinned in the tests against an exact host count) divided by
+the wall time of those steps.
+
+Printed: one JSON line (rank 0). --gpus N > 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector fp32 (packed FMA); 78.6 without packed math
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--cpu-window", type=int, default=320)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures a single GPU; multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2602_22625_amd import capi, metrics, synth
+    from paper_2602_22625_amd.fit import Fitter
+    from paper_2602_22625_amd.render import Renderer
+
+    capi.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = synth.WORKLOADS["c1"]
+    d = synth.make_workload("c1")
+    H, W, N = wl.H, wl.W, wl.N
+    p0 = torch.tensor(d["params"], device=dev)
+    idx = torch.tensor(d["idx"], device=dev)
+    atlas = torch.tensor(d["atlas"], device=dev)
+    target = torch.tensor(d["target"], device=dev)
+    log("inputs ready")
+
+    # ---------------- timed region: graph-replayed Adam steps --------------------------------
+    fit = Fitter(p0, idx, atlas, target, tile=wl.tile, lr=1e-2)
+    fit.capture()
+    for _ in range(args.warmup):
+        fit.step()
+    fit.check()
+    capi.dbmp_support_pairs(fit.R.ctx, capi.stream_handle(), reset=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fit.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fit.check()
+    pairs_timed = capi.dbmp_support_pairs(fit.R.ctx, capi.stream_handle(), reset=1)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = pairs_timed / wall
+    log("graph steps: %.3f ms/step, %.3e evals/s, psnr %.2f" % (ms_per_step, value, fit.psnr()))
+
+    # ---------------- per-kernel durations: eager steps with HIP events on the stream ----------
+    R = fit.R
+    st = torch.cuda.current_stream()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        e = evs[k]
+        e[0].record(st)
+        R.render(fit.params, idx, atlas, H, W, fit.bg, 1.0, wl.tile, image=fit.image,
+                 with_alpha=False)
+        e[1].record(st)
+        capi.dbmp_mse_grad(capi.stream_handle(), fit.image, fit.target, fit.image.numel(),
+                           fit.gimage, fit.loss_buf)
+        e[2].record(st)
+        R.backward(fit.gimage, None, out=fit.grad)
+        e[3].record(st)
+        capi.dbmp_adam_step(capi.stream_handle(), fit.params, fit.grad, fit.m, fit.v,
+                            fit.params.numel(), 1e-2, 0.9, 0.999, 1e-8, fit.step_count)
+        e[4].record(st)
+    torch.cuda.synchronize()
+    fit.check()
+    pairs_eager = capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1)
+    t_fwd = np.mean([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
+    t_mse = np.mean([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
+    t_bwd = np.mean([e[2].elapsed_time(e[3]) for e in evs]) * 1e-3
+    t_adam = np.mean([e[3].elapsed_time(e[4]) for e in evs]) * 1e-3
+    ppl = pairs_eager / args.steps  # evaluated pairs per forward (= per backward)
+    bwd_flops = ppl * metrics.BWD_FLOP_PER_PAIR
+    bwd_tflops = bwd_flops / t_bwd * 1e-12
+    log("eager: fwd(bin+raster) %.1f us, mse %.1f us, bwd %.1f us, adam %.1f us, pairs %.0f"
+        % (t_fwd * 1e6, t_mse * 1e6, t_bwd * 1e6, t_adam * 1e6, ppl))
+    # algorithmic HBM bytes of the backward launch: g (12 B/px) + per-pixel state (8 B/px)
+    # + records and lists + dparams read-modify-write; see the design notes
+    n_tile_pairs = R.pair_count()
+    bwd_bytes = 12 * H * W + 8 * H * W + 160 * N + 4 * n_tile_pairs + 32 * N + \
+        atlas.numel() * 4
+    roofline = {
+        "kernel": "k_raster_bwd (with the dL/dparams clear it launches first)",
+        "bound": "alu",
+        "achieved": round(bwd_tflops, 4),
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(bwd_tflops / PEAK_FP32_TFLOPS, 5),
+        "frac_of_nonpacked_fp32_peak": round(bwd_tflops / 78.6, 5),
+        "flop_per_pair": metrics.BWD_FLOP_PER_PAIR,
+        "pairs_per_launch": round(ppl),
+        "avg_launch_us": round(t_bwd * 1e6, 2),
+        "hbm_algorithmic_GBps": round(bwd_bytes / t_bwd * 1e-9, 2),
+        "hbm_frac": round(bwd_bytes / t_bwd * 1e-9 / PEAK_HBM_GBS, 5),
+        "traffic": None,
+    }
+
+    extra = {
+        "adam_iters_per_s_graph": round(args.steps / wall, 2),
+        "eager_breakdown_us": {"fwd_incl_binning": round(t_fwd * 1e6, 2),
+                               "mse": round(t_mse * 1e6, 2), "bwd": round(t_bwd * 1e6, 2),
+                               "adam": round(t_adam * 1e6, 2)},
+        "fwd_plus_bwd_evals_per_s_eager": round(ppl / (t_fwd + t_bwd)),
+        "psnr_after_steps": round(fit.psnr(), 3),
+        "tile_pairs_per_step": int(n_tile_pairs),
+    }
+
+    # ---------------- 2048^2 / 65,536-primitive forward + backward ---------------------------
+    if not args.no_c2:
+        d2 = synth.make_workload("c2")
+        wl2 = synth.WORKLOADS["c2"]
+        P2 = torch.tensor(d2["params"], device=dev)
+        I2 = torch.tensor(d2["idx"], device=dev)
+        A2 = torch.tensor(d2["atlas_bf16"].view(np.int16), device=dev).view(torch.bfloat16)
+        T2 = torch.tensor(d2["target"], device=dev)
+        R2 = Renderer(device=0)
+        img2, _ = R2.render(P2, I2, A2, wl2.H, wl2.W, None, 1.0, wl2.tile, with_alpha=False)
+        g2 = torch.empty_like(img2)
+        capi.dbmp_mse_grad(capi.stream_handle(), img2, T2, img2.numel(), g2, None)
+        R2.check_each = False
+        out2 = torch.empty(wl2.N, 8, device=dev)
+        reps = 10
+        ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        capi.dbmp_support_pairs(R2.ctx, capi.stream_handle(), reset=1)
+        for k in range(reps + 2):
+            e = ev2[k - 2] if k >= 2 else None
+            if e: e[0].record(st)
+            R2.render(P2, I2, A2, wl2.H, wl2.W, None, 1.0, wl2.tile, image=img2,
+                      with_alpha=False)
+            if e: e[1].record(st)
+            R2.backward(g2, None, out=out2)
+            if e: e[2].record(st)
+        torch.cuda.synchronize()
+        R2.check()
+        pp2 = capi.dbmp_support_pairs(R2.ctx, capi.stream_handle(), reset=1) / (reps + 2)
+        f2 = np.median([e[0].elapsed_time(e[1]) for e in ev2]) * 1e-3
+        b2 = np.median([e[1].elapsed_time(e[2]) for e in ev2]) * 1e-3
+        extra["c2_2048sq_65536prims"] = {
+            "fwd_incl_binning_ms": round(f2 * 1e3, 4), "bwd_ms": round(b2 * 1e3, 4),
+            "evals_per_pass": round(pp2), "fwd_plus_bwd_evals_per_s": round(pp2 / (f2 + b2)),
+            "tile": wl2.tile, "atlas": "64x128x128 bf16",
+            "peak_mem_GB": round(torch.cuda.max_memory_allocated() / 1e9, 3)}
+        log("c2: fwd %.3f ms bwd %.3f ms" % (f2 * 1e3, b2 * 1e3))
+        del R2
+
+    # ---------------- CPU baseline: the FP64 oracle on a window of the same workload -------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        w = args.cpu_window
+        crop = ((W - w) // 2, (H - w) // 2, w, w)
+        boxes = metrics.nonzero_boxes(d["atlas"])
+        sp = metrics.support_pairs(d["params"], 64, 64, H, W, crop=crop, idx=d["idx"],
+                                   boxes=boxes)
+        rng = np.random.default_rng(0)
+        gI = rng.standard_normal((3, w, w))
+        t0 = time.perf_counter()
+        oracle.render(d["params"], d["idx"], d["atlas"], H, W, crop=crop)
+        oracle.render_backward(d["params"], d["idx"], d["atlas"], H, W, gI, crop=crop)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(sp / tc, 1), "unit": "primitive-pixel evals/s", "cores":
+               oracle.threads(), "kind": "oracle",
+               "sample": "forward+backward of a %dx%d window of the 512x512 workload with all "
+                         "4096 primitives (FP64, every primitive at every pixel), %d evaluated "
+                         "pairs, %.2f s" % (w, w, sp, tc)}
+        log("cpu baseline %.3e evals/s on %d threads" % (sp / tc, oracle.threads()))
+
+    out = {
+        "metric": "fwd+bwd primitive-pixel evals/s (+ Adam iters/s)",
+        "value": round(value),
+        "unit": "primitive-pixel evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512x512 RGB target, 4096 primitives, 16 64x64 fp32 star/stroke "
+                               "bitmaps, 16x16 tiles, plain Adam lr 1e-2 on MSE, one Adam "
+                               "iteration per step replayed from a HIP graph",
+                   "H": H, "W": W, "N": N, "tile": wl.tile},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,31 +118,40 @@ int dbmp_render_batched(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
                         int atlas_dtype, const float *bg, float alpha_max, int tile,
                         float *image, float *alpha);
 
-/* Synchronises `stream` and reports device-side flags of the last forward/backward:
- * DBMP_EOVERFLOW, DBMP_EINVAL (atlas index out of range), DBMP_ENONFINITE, or DBMP_OK.
- * Clears nothing: the next forward resets the flags. */
+/* Synchronises `stream` and reports the device-side errors raised by any forward since the
+ * previous dbmp_check: DBMP_EOVERFLOW (a forward needed more pairs than the buffer holds; its
+ * image is not valid), DBMP_EINVAL (atlas index out of range), DBMP_ENONFINITE, or DBMP_OK.
+ * The reported errors are cleared. */
 int dbmp_check(dbmp_ctx *ctx, dbmp_stream stream);
 
-/* Number of (tile, primitive) pairs of the last forward. Synchronises `stream`. */
+/* Largest number of (tile, primitive) pairs any forward needed since the last dbmp_reserve (or
+ * dbmp_create): the size to pass to dbmp_reserve after DBMP_EOVERFLOW. Synchronises `stream`. */
 long long dbmp_pair_count(dbmp_ctx *ctx, dbmp_stream stream);
+
+/* Number of (pixel, primitive) pairs evaluated by all forwards on this context since it was
+ * created or last reset: pairs where the primitive's bilinear footprint at the pixel reads at
+ * least one non-zero texel (elsewhere M and its derivatives are exactly zero, Supp. Eqs. S1-S3).
+ * Synchronises `stream`; reset != 0 zeroes the count afterwards (synchronously). -1 on error. */
+long long dbmp_support_pairs(dbmp_ctx *ctx, dbmp_stream stream, int reset);
 
 /* Message of the last error on this context ("" if none). Valid until the next call. */
 const char *dbmp_last_error(const dbmp_ctx *ctx);
 
 /*
  * Mean-squared-error gradient over n values (the `mse` loss of the paper's configuration, Supp.
- * Table S1): grad[i] = 2 (image[i] - target[i]) / n. If loss_sum != NULL, sum_i (image[i] -
- * target[i])^2 is ADDED to *loss_sum (device float32; the caller zeroes it).
+ * Table S1): grad[i] = 2 (image[i] - target[i]) / n. If loss != NULL it points to THREE device
+ * float32 (zero before the first call; [1] and [2] are scratch the call leaves at zero) and
+ * loss[0] receives sum_i (image[i] - target[i])^2.
  */
 int dbmp_mse_grad(dbmp_stream stream, const float *image, const float *target, long long n,
-                  float *grad, float *loss_sum);
+                  float *grad, float *loss);
 
 /*
  * One Adam step (Kingma & Ba, Algorithm 1; the optimiser of Supp. Table S1 with a flat rate) on
- * n float32 values in place: m, v are the moment buffers (zero before the first step), *step is
- * a device int32 counter of steps already taken (zero before the first step); this call uses
- * t = *step + 1 for the bias correction and then increments *step on the device, so the call
- * can be replayed from a captured graph.
+ * n float32 values in place: m, v are the moment buffers (zero before the first step). `step`
+ * points to TWO device int32: step[0] counts the steps already taken and step[1] is scratch for
+ * the kernel; both must be zero before the first step. The call uses t = step[0] + 1 for the
+ * bias correction and advances step[0] on the device, so it can be replayed from a graph.
  */
 int dbmp_adam_step(dbmp_stream stream, float *params, const float *grad, float *m, float *v,
                    long long n, float lr, float beta1, float beta2, float eps, int32_t *step);

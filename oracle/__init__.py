@@ -48,6 +48,8 @@ def _load():
         lib.oracle_pixel_trace.restype = i
         lib.oracle_support_pairs.argtypes = [i, P, P, i, i, i, i, i, i, i, i]
         lib.oracle_support_pairs.restype = ctypes.c_longlong
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = i
         _lib = lib
     return _lib
 
@@ -128,6 +130,10 @@ def pixel_trace(params, idx, atlas, px, py, alpha_max=1.0):
     if n < 0:
         raise ValueError("oracle_pixel_trace: invalid arguments")
     return ks[:n].copy(), al[:n].copy(), Ts[:n].copy(), float(tf[0])
+
+
+def threads():
+    return int(_load().oracle_threads())
 
 
 def support_pairs_bruteforce(params, Hb, Wb, H, W, crop=None, threads=0):

@@ -271,6 +271,16 @@ int oracle_pixel_trace(int N, const double *params, const int *idx, const double
     return n;
 }
 
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /*
  * Exact number of (pixel, primitive) pairs of the crop window where the primitive's bilinear
  * sampler reads at least one lattice point inside its bitmap (the pairs the method evaluates).

@@ -55,6 +55,7 @@ def load():
         "dbmp_render_batched": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P], I),
         "dbmp_check": ([P, P], I),
         "dbmp_pair_count": ([P, P], LL),
+        "dbmp_support_pairs": ([P, P, I], LL),
         "dbmp_last_error": ([P], ctypes.c_char_p),
         "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
         "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P], I),
@@ -138,13 +139,17 @@ def dbmp_pair_count(ctx, stream):
     return int(load().dbmp_pair_count(ctx, stream))
 
 
+def dbmp_support_pairs(ctx, stream, reset=0):
+    return int(load().dbmp_support_pairs(ctx, stream, int(reset)))
+
+
 def dbmp_last_error(ctx):
     return load().dbmp_last_error(ctx).decode()
 
 
-def dbmp_mse_grad(stream, image, target, n, grad, loss_sum):
+def dbmp_mse_grad(stream, image, target, n, grad, loss):
     return _chk(None, load().dbmp_mse_grad(stream, ptr(image), ptr(target), int(n), ptr(grad),
-                                           ptr(loss_sum)))
+                                           ptr(loss)))
 
 
 def dbmp_adam_step(stream, params, grad, m, v, n, lr, beta1, beta2, eps, step):

@@ -20,8 +20,11 @@ namespace dbmp {
 // ------------------------------------------------------------------------------------------
 // k_setup
 // ------------------------------------------------------------------------------------------
+#define SETUP_THREADS 1024
+#define SETUP_BATCH 8
+
 template <typename TexT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SETUP_THREADS)
 k_setup(const TexT *__restrict__ atlas, int B, int Hb, int Wb, TexT *__restrict__ pad, int Wp,
         int *__restrict__ box, int *__restrict__ tile_count, int n_tiles, int *__restrict__ flags)
 {
@@ -31,43 +34,60 @@ k_setup(const TexT *__restrict__ atlas, int B, int Hb, int Wb, TexT *__restrict_
         const TexT *src = atlas + (size_t)b * Hb * Wb;
         TexT *dst = pad + (size_t)b * Hp * Wp;
         int xlo = INT_MAX, xhi = INT_MIN, ylo = INT_MAX, yhi = INT_MIN, bad = 0;
-        for (int i = threadIdx.x; i < Hp * Wp; i += blockDim.x) {
-            const int r = i / Wp - 1, c = i % Wp - 1;
-            TexT v = TexT(0);
-            if (r >= 0 && r < Hb && c >= 0 && c < Wb) {
-                v = src[(size_t)r * Wb + c];
-                const float f = texel<TexT>(v);
-                if (!isfinite(f)) { bad = 1; v = TexT(0); }
-                if (f != 0.0f) {
-                    xlo = min(xlo, c); xhi = max(xhi, c);
-                    ylo = min(ylo, r); yhi = max(yhi, r);
-                }
+        const int total = Hp * Wp;
+        for (int base = 0; base < total; base += SETUP_THREADS * SETUP_BATCH) {
+            TexT v[SETUP_BATCH];
+            int rr[SETUP_BATCH], cc[SETUP_BATCH];
+#pragma unroll
+            for (int q = 0; q < SETUP_BATCH; ++q) {  // issue every load of the batch first
+                const int i = base + q * SETUP_THREADS + threadIdx.x;
+                rr[q] = i / Wp - 1;
+                cc[q] = i % Wp - 1;
+                const bool inside = i < total && rr[q] >= 0 && rr[q] < Hb && cc[q] >= 0 &&
+                                    cc[q] < Wb;
+                v[q] = inside ? src[(size_t)rr[q] * Wb + cc[q]] : TexT(0);
             }
-            dst[i] = v;
+#pragma unroll
+            for (int q = 0; q < SETUP_BATCH; ++q) {
+                const int i = base + q * SETUP_THREADS + threadIdx.x;
+                if (i >= total) continue;
+                const float f = texel<TexT>(v[q]);
+                if (!isfinite(f)) { bad = 1; v[q] = TexT(0); }
+                if (f != 0.0f && isfinite(f)) {
+                    xlo = min(xlo, cc[q]); xhi = max(xhi, cc[q]);
+                    ylo = min(ylo, rr[q]); yhi = max(yhi, rr[q]);
+                }
+                dst[i] = v[q];
+            }
         }
-        __shared__ int s[4];
-        if (threadIdx.x == 0) { s[0] = INT_MAX; s[1] = INT_MIN; s[2] = INT_MAX; s[3] = INT_MIN; }
+        __shared__ int s[5];
+        if (threadIdx.x == 0) {
+            s[0] = INT_MAX; s[1] = INT_MIN; s[2] = INT_MAX; s[3] = INT_MIN; s[4] = 0;
+        }
         __syncthreads();
-        if (xlo <= xhi) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            xlo = min(xlo, __shfl_xor(xlo, o)); xhi = max(xhi, __shfl_xor(xhi, o));
+            ylo = min(ylo, __shfl_xor(ylo, o)); yhi = max(yhi, __shfl_xor(yhi, o));
+        }
+        if ((threadIdx.x & 63) == 0 && xlo <= xhi) {
             atomicMin(&s[0], xlo); atomicMax(&s[1], xhi);
             atomicMin(&s[2], ylo); atomicMax(&s[3], yhi);
         }
-        if (bad) atomicOr(&flags[F_NONFINITE], 1);
+        if (bad) s[4] = 1;
         __syncthreads();
         if (threadIdx.x == 0) {
-            box[4 * b + 0] = s[0]; box[4 * b + 1] = s[1];
+            // a bitmap holding a non-finite texel is marked; primitives using it raise the flag
+            box[4 * b + 0] = s[4] ? INT_MIN : s[0]; box[4 * b + 1] = s[1];
             box[4 * b + 2] = s[2]; box[4 * b + 3] = s[3];
         }
     } else {
         const int nb = gridDim.x - B, ib = blockIdx.x - B;
         for (int i = ib * blockDim.x + threadIdx.x; i < n_tiles; i += nb * blockDim.x)
-            tile_count[i] = 0;
-        if (ib == 0 && threadIdx.x < F_COUNT && threadIdx.x != F_NONFINITE) flags[threadIdx.x] = 0;
+            tile_count[(size_t)i * CNT_STRIDE] = 0;
+        if (ib == 0 && threadIdx.x < F_S_OVERFLOW) flags[threadIdx.x] = 0;  // per-forward flags
     }
 }
-
-// F_NONFINITE is raised by k_setup itself, so it is cleared before k_setup runs.
-__global__ void k_clear_flag(int *__restrict__ flags) { flags[F_NONFINITE] = 0; }
 
 // ------------------------------------------------------------------------------------------
 // Separating-axis test of the support parallelogram against a tile's pixel centres. U' and V'
@@ -117,13 +137,21 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
         for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
         const int k = idx[g];
         bool ok = true;
-        if (k < 0 || k >= B) { atomicOr(&flags[F_BADIDX], 1); ok = false; }
+        if (k < 0 || k >= B) {
+            atomicOr(&flags[F_BADIDX], 1);
+            atomicOr(&flags[F_S_BADIDX], 1);
+            ok = false;
+        }
         bool fin = true;
 #pragma unroll
         for (int j = 0; j < 8; ++j) fin = fin && isfinite(p[j]);
         const double s = exp((double)p[2]);
         if (!(s > 0.0) || !isfinite(s)) fin = false;  // scale underflows or overflows
-        if (!fin) { atomicOr(&flags[F_NONFINITE], 1); ok = false; }
+        if (!fin) {
+            atomicOr(&flags[F_NONFINITE], 1);
+            atomicOr(&flags[F_S_NONFINITE], 1);
+            ok = false;
+        }
         if (ok) {
             double st, ct;
             sincos((double)p[3], &st, &ct);
@@ -146,8 +174,14 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
             rec.cb = (float)(1.0 / (1.0 + exp(-(double)p[7])));
             const int Hp = Hb + 2;
             rec.tex = k * Hp * Wp;
-            const int xlo = box[4 * k], xhi = box[4 * k + 1];
+            int xlo = box[4 * k];
+            const int xhi = box[4 * k + 1];
             const int ylo = box[4 * k + 2], yhi = box[4 * k + 3];
+            if (xlo == INT_MIN) {  // the bitmap holds a non-finite texel (read as 0)
+                atomicOr(&flags[F_NONFINITE], 1);
+                atomicOr(&flags[F_S_NONFINITE], 1);
+                xlo = 0;
+            }
             if (xlo <= xhi && D.W > 0 && D.H > 0) {
                 // floor(U') in [xlo, xhi + 1] reads at least one non-zero texel (padded columns
                 // xlo + 1 .. xhi + 1); elsewhere M and its derivatives are exactly zero.
@@ -170,19 +204,33 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
                 if (fx0 <= fx1 && fy0 <= fy1) {
                     rec.tx0 = (int)fx0 / TS; rec.tx1 = (int)fx1 / TS;
                     rec.ty0 = (int)fy0 / TS; rec.ty1 = (int)fy1 / TS;
-                    for (int ty = rec.ty0; ty <= rec.ty1; ++ty) {
-                        const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, D.H - 1);
-                        for (int tx = rec.tx0; tx <= rec.tx1; ++tx) {
-                            const int X0 = tx * TS, X1 = min(X0 + TS - 1, D.W - 1);
-                            if (tile_hits(rec, X0, X1, Y0, Y1))
-                                atomicAdd(&tile_count[D.tile_off + ty * D.ntx + tx], 1);
-                        }
-                    }
                 }
             }
         }
     }
     recs[g] = rec;
+}
+
+// k_count: 16 lanes per primitive walk its tile span and count the tiles its support hits.
+__global__ void __launch_bounds__(256)
+k_count(const PrimRec *__restrict__ recs, long long n_rows, const ImgDev *__restrict__ imgs,
+        int TS, int *__restrict__ tile_count)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long g = t / 16;
+    const int l = (int)(t % 16);
+    if (g >= n_rows) return;
+    const PrimRec &r = recs[g];
+    if (r.tx0 > r.tx1) return;
+    const ImgDev D = imgs[r.img];
+    const int nx = r.tx1 - r.tx0 + 1, ny = r.ty1 - r.ty0 + 1;
+    for (int k = l; k < nx * ny; k += 16) {
+        const int tx = r.tx0 + k % nx, ty = r.ty0 + k / nx;
+        const int X0 = tx * TS, X1 = min(X0 + TS - 1, D.W - 1);
+        const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, D.H - 1);
+        if (tile_hits(r, X0, X1, Y0, Y1))
+            atomicAdd(&tile_count[(size_t)(D.tile_off + ty * D.ntx + tx) * CNT_STRIDE], 1);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -205,7 +253,7 @@ k_scan(int *__restrict__ tile_count, int *__restrict__ tile_start, int n_tiles,
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int j = base + t * PER + i;
-            v[i] = j < n_tiles ? tile_count[j] : 0;
+            v[i] = j < n_tiles ? tile_count[(size_t)j * CNT_STRIDE] : 0;
             loc += v[i];
         }
         // inclusive wave scan of loc
@@ -225,7 +273,7 @@ k_scan(int *__restrict__ tile_count, int *__restrict__ tile_start, int n_tiles,
             const int j = base + t * PER + i;
             if (j < n_tiles) {
                 tile_start[j] = (int)(run < INT_MAX ? run : INT_MAX);
-                tile_count[j] = 0;
+                tile_count[(size_t)j * CNT_STRIDE] = 0;
             }
             run += v[i];
         }
@@ -235,33 +283,45 @@ k_scan(int *__restrict__ tile_count, int *__restrict__ tile_start, int n_tiles,
     }
     if (t == 0) {
         const long long total = carry_s;
-        flags[F_TOTAL] = (int)(total < INT_MAX ? total : INT_MAX);
-        if (total > pair_cap) flags[F_OVERFLOW] = 1;
+        const int tc = (int)(total < INT_MAX ? total : INT_MAX);
+        flags[F_TOTAL] = tc;
+        atomicMax(&flags[F_S_TOTALMAX], tc);
+        if (total > pair_cap) {
+            flags[F_OVERFLOW] = 1;
+            flags[F_S_OVERFLOW] = 1;
+        }
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// k_emit: same tile walk as k_prep, appending the primitive's row to each hit tile's list.
+// k_emit: appends each primitive's row to the lists of the tiles it hits. Sixteen lanes share
+// a primitive and split its tile span, so its (returning) atomics are issued together instead
+// of one after another.
 // ------------------------------------------------------------------------------------------
+#define EMIT_LANES 16
+
 __global__ void __launch_bounds__(256)
 k_emit(const PrimRec *__restrict__ recs, long long n_rows, const ImgDev *__restrict__ imgs, int TS,
        const int *__restrict__ tile_start, int *__restrict__ tile_fill, int *__restrict__ pairs,
        long long pair_cap)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long g = t / EMIT_LANES;
+    const int l = (int)(t % EMIT_LANES);
     if (g >= n_rows) return;
-    const PrimRec r = recs[g];
+    const PrimRec &r = recs[g];
     if (r.tx0 > r.tx1) return;
     const ImgDev D = imgs[r.img];
-    for (int ty = r.ty0; ty <= r.ty1; ++ty) {
+    const int nx = r.tx1 - r.tx0 + 1, ny = r.ty1 - r.ty0 + 1;
+    for (int k = l; k < nx * ny; k += EMIT_LANES) {
+        const int tx = r.tx0 + k % nx, ty = r.ty0 + k / nx;
+        const int X0 = tx * TS, X1 = min(X0 + TS - 1, D.W - 1);
         const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, D.H - 1);
-        for (int tx = r.tx0; tx <= r.tx1; ++tx) {
-            const int X0 = tx * TS, X1 = min(X0 + TS - 1, D.W - 1);
-            if (!tile_hits(r, X0, X1, Y0, Y1)) continue;
-            const int t = D.tile_off + ty * D.ntx + tx;
-            const long long pos = (long long)tile_start[t] + atomicAdd(&tile_fill[t], 1);
-            if (pos < pair_cap) pairs[pos] = (int)g;
-        }
+        if (!tile_hits(r, X0, X1, Y0, Y1)) continue;
+        const int tt = D.tile_off + ty * D.ntx + tx;
+        const long long pos =
+            (long long)tile_start[tt] + atomicAdd(&tile_fill[(size_t)tt * CNT_STRIDE], 1);
+        if (pos < pair_cap) pairs[pos] = (int)g;
     }
 }
 
@@ -314,7 +374,7 @@ k_sort(int *__restrict__ pairs, const int *__restrict__ tile_start,
     const int t = blockIdx.x;
     if (t >= n_tiles) return;
     const int lane = threadIdx.x;
-    const int n = tile_count[t];
+    const int n = tile_count[(size_t)t * CNT_STRIDE];
     if (n <= 1) return;
     int *seg = pairs + tile_start[t];
     if (n <= 64) {
@@ -343,23 +403,25 @@ k_sort(int *__restrict__ pairs, const int *__restrict__ tile_start,
 
 hipError_t launch_binning(const BinArgs &a, hipStream_t st)
 {
-    k_clear_flag<<<1, 1, 0, st>>>(a.flags);
-    const int zb = a.n_tiles > 0 ? min((a.n_tiles + 255) / 256, 1024) : 1;
+    const int zb = a.n_tiles > 0 ? min((a.n_tiles + SETUP_THREADS - 1) / SETUP_THREADS, 256) : 1;
     if (a.dtype == 0)
-        k_setup<float><<<a.B + zb, 256, 0, st>>>((const float *)a.atlas, a.B, a.Hb, a.Wb,
+        k_setup<float><<<a.B + zb, SETUP_THREADS, 0, st>>>((const float *)a.atlas, a.B, a.Hb, a.Wb,
                                                   (float *)a.atlas_pad, a.Wp, a.box, a.tile_count,
                                                   a.n_tiles, a.flags);
     else
-        k_setup<uint16_t><<<a.B + zb, 256, 0, st>>>((const uint16_t *)a.atlas, a.B, a.Hb, a.Wb,
+        k_setup<uint16_t><<<a.B + zb, SETUP_THREADS, 0, st>>>((const uint16_t *)a.atlas, a.B, a.Hb, a.Wb,
                                                      (uint16_t *)a.atlas_pad, a.Wp, a.box,
                                                      a.tile_count, a.n_tiles, a.flags);
     if (a.n_rows > 0)
         k_prep<<<(unsigned)((a.n_rows + 255) / 256), 256, 0, st>>>(
             a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
             a.alpha_max, a.TS, a.recs, a.tile_count, a.flags);
+    if (a.n_rows > 0)
+        k_count<<<(unsigned)((a.n_rows * 16 + 255) / 256), 256, 0, st>>>(a.recs, a.n_rows, a.imgs,
+                                                                          a.TS, a.tile_count);
     k_scan<<<1, 1024, 0, st>>>(a.tile_count, a.tile_start, a.n_tiles, a.pair_cap, a.flags);
     if (a.n_rows > 0)
-        k_emit<<<(unsigned)((a.n_rows + 255) / 256), 256, 0, st>>>(
+        k_emit<<<(unsigned)((a.n_rows * EMIT_LANES + 255) / 256), 256, 0, st>>>(
             a.recs, a.n_rows, a.imgs, a.TS, a.tile_start, a.tile_count, a.pairs, a.pair_cap);
     if (a.n_tiles > 0)
         k_sort<<<a.n_tiles, 64, 0, st>>>(a.pairs, a.tile_start, a.tile_count, a.n_tiles, a.flags);

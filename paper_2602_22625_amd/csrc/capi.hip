@@ -25,7 +25,7 @@ struct Buf {
 struct dbmp_ctx {
     int device = 0;
     std::string err;
-    Buf recs, tile_count, tile_start, pairs, saveK, saveT, atlas_pad, box, imgs, flags;
+    Buf recs, tile_count, tile_start, pairs, saveK, saveT, atlas_pad, box, imgs, flags, counter;
     long long pair_cap = 0;
     std::vector<ImgDev> imgs_uploaded;  // what the device copy of the descriptors holds
     // state of the last forward, for the backward
@@ -154,7 +154,8 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     int rc;
     const size_t ni = imgs.size();
     if ((rc = ensure(c, c->recs, sizeof(PrimRec) * (size_t)n_rows, st, "records"))) return rc;
-    if ((rc = ensure(c, c->tile_count, 4 * (size_t)tiles, st, "tile_count"))) return rc;
+    if ((rc = ensure(c, c->tile_count, 4 * CNT_STRIDE * (size_t)tiles, st, "tile_count")))
+        return rc;
     if ((rc = ensure(c, c->tile_start, 4 * (size_t)tiles, st, "tile_start"))) return rc;
     if ((rc = ensure(c, c->pairs, 4 * (size_t)c->pair_cap, st, "pairs"))) return rc;
     if ((rc = ensure(c, c->saveK, 4 * (size_t)n_pix, st, "saveK"))) return rc;
@@ -199,6 +200,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.bg = bg; ra.bg_pp = bg_pp; ra.image = image; ra.alpha = alpha;
     ra.saveK = (int *)c->saveK.p; ra.saveT = (float *)c->saveT.p;
     ra.flags = (const int *)c->flags.p; ra.TS = tile;
+    ra.pair_counter = (unsigned long long *)c->counter.p;
     e = launch_raster_fwd(ra, st);
     if (e != hipSuccess) return hip_fail(c, e, "forward launch");
     c->have_fwd = true;
@@ -225,6 +227,10 @@ int dbmp_create(dbmp_ctx **out, int device, long long pair_capacity)
     int rc = ensure(c, c->flags, 4 * F_COUNT, nullptr, "flags");
     if (rc) { delete c; return rc; }
     (void)hipMemset(c->flags.p, 0, 4 * F_COUNT);
+    rc = ensure(c, c->counter, 8 * DBMP_COUNTER_SLOTS, nullptr, "counter");
+    if (rc) { delete c; return rc; }
+    (void)hipMemset(c->counter.p, 0, 8 * DBMP_COUNTER_SLOTS);
+    (void)hipDeviceSynchronize();
     rc = ensure(c, c->pairs, 4 * (size_t)c->pair_cap, nullptr, "pairs");
     if (rc) { delete c; return rc; }
     c->pair_cap = (long long)(c->pairs.cap / 4);
@@ -239,7 +245,7 @@ int dbmp_destroy(dbmp_ctx *c)
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
         Buf *bs[] = {&c->recs, &c->tile_count, &c->tile_start, &c->pairs, &c->saveK,
-                     &c->saveT, &c->atlas_pad, &c->box, &c->imgs, &c->flags};
+                     &c->saveT, &c->atlas_pad, &c->box, &c->imgs, &c->flags, &c->counter};
         for (Buf *b : bs)
             if (b->p) (void)hipFree(b->p);
     }
@@ -257,6 +263,9 @@ int dbmp_reserve(dbmp_ctx *c, long long pair_capacity)
     int rc = ensure(c, c->pairs, 4 * (size_t)pair_capacity, nullptr, "pairs");
     if (rc) return rc;
     c->pair_cap = std::min<long long>((long long)(c->pairs.cap / 4), INT_MAX - 1);
+    e = hipMemset((int *)c->flags.p + F_S_TOTALMAX, 0, sizeof(int));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "flag reset");
     c->have_fwd = false;  // the lists of the last forward are gone
     return DBMP_OK;
 }
@@ -318,12 +327,18 @@ int dbmp_check(dbmp_ctx *c, dbmp_stream stream)
     int f[F_COUNT];
     e = hipMemcpy(f, c->flags.p, sizeof(f), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "flag readback");
-    if (f[F_OVERFLOW])
-        return fail(c, DBMP_EOVERFLOW, "pair buffer too small: " + std::to_string(f[F_TOTAL]) +
+    if (f[F_S_OVERFLOW] | f[F_S_BADIDX] | f[F_S_NONFINITE]) {
+        e = hipMemset((int *)c->flags.p + F_S_OVERFLOW, 0, 3 * sizeof(int));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(c, e, "flag reset");
+    }
+    if (f[F_S_OVERFLOW])
+        return fail(c, DBMP_EOVERFLOW, "pair buffer too small: " +
+                                           std::to_string(f[F_S_TOTALMAX]) +
                                            " pairs needed, capacity " +
                                            std::to_string(c->pair_cap));
-    if (f[F_BADIDX]) return fail(c, DBMP_EINVAL, "atlas index out of range");
-    if (f[F_NONFINITE]) return fail(c, DBMP_ENONFINITE, "non-finite parameter or texel");
+    if (f[F_S_BADIDX]) return fail(c, DBMP_EINVAL, "atlas index out of range");
+    if (f[F_S_NONFINITE]) return fail(c, DBMP_ENONFINITE, "non-finite parameter or texel");
     return DBMP_OK;
 }
 
@@ -334,7 +349,24 @@ long long dbmp_pair_count(dbmp_ctx *c, dbmp_stream stream)
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return -1;
     int f[F_COUNT];
     if (hipMemcpy(f, c->flags.p, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess) return -1;
-    return f[F_TOTAL];
+    return f[F_S_TOTALMAX];
+}
+
+long long dbmp_support_pairs(dbmp_ctx *c, dbmp_stream stream, int reset)
+{
+    if (!c) return -1;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return -1;
+    std::vector<unsigned long long> slots(DBMP_COUNTER_SLOTS);
+    if (hipMemcpy(slots.data(), c->counter.p, 8 * DBMP_COUNTER_SLOTS, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return -1;
+    unsigned long long v = 0;
+    for (unsigned long long x : slots) v += x;
+    if (reset && hipMemset(c->counter.p, 0, 8 * DBMP_COUNTER_SLOTS) != hipSuccess) return -1;
+    if (reset && hipDeviceSynchronize() != hipSuccess) return -1;
+    return (long long)v;
 }
 
 const char *dbmp_last_error(const dbmp_ctx *c) { return c ? c->err.c_str() : "null context"; }

@@ -8,19 +8,29 @@ namespace dbmp {
 
 // Device-side flag slots (int32 each) kept in the context workspace.
 enum Flag : int {
-    F_OVERFLOW = 0,   // more (tile, primitive) pairs than the pair buffer holds
-    F_BADIDX = 1,     // an atlas index outside [0, B)
-    F_NONFINITE = 2,  // a non-finite parameter / texel / scale
-    F_TOTAL = 3,      // number of (tile, primitive) pairs of the last forward (clamped to INT_MAX)
-    F_QFWD = 4,       // persistent-queue counters
-    F_QBWD = 5,
-    F_STEP_SPARE = 6,
-    F_COUNT = 8
+    // per forward (reset at the start of every forward)
+    F_OVERFLOW = 0,     // more (tile, primitive) pairs than the pair buffer holds
+    F_BADIDX = 1,       // an atlas index outside [0, B)
+    F_NONFINITE = 2,    // a non-finite parameter / texel / scale
+    F_TOTAL = 3,        // number of (tile, primitive) pairs of this forward (clamped to INT_MAX)
+    // sticky (raised by any forward; errors cleared by dbmp_check, the maximum by dbmp_reserve)
+    F_S_OVERFLOW = 4,
+    F_S_BADIDX = 5,
+    F_S_NONFINITE = 6,
+    F_S_TOTALMAX = 7,   // largest per-forward pair count since the last reserve
+    F_COUNT = 16
 };
 
 // Transmittance threshold of the backward: layers in front of which T has fallen below TAU
 // (2^-64) get a zero gradient; their exact gradient is below TAU times an O(1) factor.
 #define DBMP_TAU 5.42101086242752217e-20f
+
+// Per-tile pair counters are updated by device-scope atomics, which serialise per cache line;
+// each counter therefore gets a 128-byte line of its own (tile t at tile_count[t * CNT_STRIDE]).
+#define CNT_STRIDE 32
+
+// The evaluated-pair counter is spread over this many 64-bit slots (summed when read).
+#define DBMP_COUNTER_SLOTS 1024
 
 // One image of a (possibly batched) launch.
 struct ImgDev {
@@ -127,6 +137,7 @@ struct RasterArgs {
     long long n_param_floats;
     const int *flags;
     int TS;
+    unsigned long long *pair_counter;  // cumulative count of evaluated (pixel, primitive) pairs
 };
 
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);

@@ -13,12 +13,25 @@ k_mse_grad(const float4 *__restrict__ img, const float4 *__restrict__ tgt, long 
     float acc = 0.f;
     const long long stride = (long long)gridDim.x * blockDim.x;
     float4 *g4 = (float4 *)grad;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        const float4 a = img[i], b = tgt[i];
-        const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
-        g4[i] = make_float4(scale * d.x, scale * d.y, scale * d.z, scale * d.w);
-        acc = fmaf(d.x, d.x, acc); acc = fmaf(d.y, d.y, acc);
-        acc = fmaf(d.z, d.z, acc); acc = fmaf(d.w, d.w, acc);
+    constexpr int U = 4;  // float4 loads in flight per thread
+    for (long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; i0 < n4;
+         i0 += U * stride) {
+        float4 a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * stride;
+            if (i < n4) { a[u] = img[i]; b[u] = tgt[i]; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * stride;
+            if (i >= n4) continue;
+            const float4 d = make_float4(a[u].x - b[u].x, a[u].y - b[u].y, a[u].z - b[u].z,
+                                         a[u].w - b[u].w);
+            g4[i] = make_float4(scale * d.x, scale * d.y, scale * d.z, scale * d.w);
+            acc = fmaf(d.x, d.x, acc); acc = fmaf(d.y, d.y, acc);
+            acc = fmaf(d.z, d.z, acc); acc = fmaf(d.w, d.w, acc);
+        }
     }
     for (long long i = 4 * n4 + (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += stride) {
@@ -31,30 +44,54 @@ k_mse_grad(const float4 *__restrict__ img, const float4 *__restrict__ tgt, long 
     __shared__ float ws[4];
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) unsafeAtomicAdd(loss_sum, ws[0] + ws[1] + ws[2] + ws[3]);
+    if (threadIdx.x == 0) {
+        // loss_sum[2] accumulates the block sums, loss_sum[1] counts finished blocks; the last
+        // block publishes the total in loss_sum[0] and re-arms both for the next call
+        unsafeAtomicAdd(loss_sum + 2, ws[0] + ws[1] + ws[2] + ws[3]);
+        __threadfence();
+        unsigned int *cnt = (unsigned int *)(loss_sum + 1);
+        if (atomicAdd(cnt, 1u) == gridDim.x - 1) {
+            __threadfence();
+            loss_sum[0] = __hip_atomic_load(loss_sum + 2, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+            loss_sum[2] = 0.f;
+            *cnt = 0u;
+            __threadfence();
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256)
 k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
        float *__restrict__ v, long long n, float lr, float b1, float b2, float eps,
-       const int *__restrict__ step)
+       int *__restrict__ step, unsigned int *__restrict__ done)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const int t = *step + 1;
-    // bias corrections 1 - beta^t, evaluated in float64 once per thread (cheap, exact enough)
-    const float c1 = (float)(1.0 - pow((double)b1, (double)t));
-    const float c2 = (float)(1.0 - pow((double)b2, (double)t));
-    const float gi = g[i];
-    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
-    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
-    m[i] = mi;
-    v[i] = vi;
-    const float mhat = mi / c1, vhat = vi / c2;
-    p[i] = p[i] - lr * mhat / (sqrtf(vhat) + eps);
+    if (i < n) {
+        // bias corrections 1 - beta^t, evaluated in float64
+        const float c1 = (float)(1.0 - pow((double)b1, (double)t));
+        const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+        const float gi = g[i];
+        const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+        const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+        m[i] = mi;
+        v[i] = vi;
+        const float mhat = mi / c1, vhat = vi / c2;
+        p[i] = p[i] - lr * mhat / (sqrtf(vhat) + eps);
+    }
+    // The last block to finish advances the step counter (every block has read it by then)
+    // and re-arms the completion counter for the next call.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(done, 1u) == gridDim.x - 1) {
+            *step = t;
+            *done = 0u;
+            __threadfence();
+        }
+    }
 }
-
-__global__ void k_step_inc(int *__restrict__ step) { *step += 1; }
 
 }  // namespace dbmp
 
@@ -68,8 +105,8 @@ extern "C" int dbmp_mse_grad(dbmp_stream stream, const float *image, const float
     hipStream_t st = (hipStream_t)stream;
     const bool aligned = (((uintptr_t)image | (uintptr_t)target | (uintptr_t)grad) & 15) == 0;
     const long long n4 = aligned ? n / 4 : 0;
-    long long blocks = (n + 1023) / 1024;
-    if (blocks > 4096) blocks = 4096;
+    long long blocks = (n + 4095) / 4096;
+    if (blocks > 256) blocks = 256;
     k_mse_grad<<<(unsigned)blocks, 256, 0, st>>>((const float4 *)image, (const float4 *)target,
                                                  n4, image, target, n, grad, 2.0f / (float)n,
                                                  loss_sum);
@@ -84,9 +121,7 @@ extern "C" int dbmp_adam_step(dbmp_stream stream, float *params, const float *gr
     if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
         return DBMP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    if (n > 0)
-        k_adam<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(params, grad, m, v, n, lr, beta1,
-                                                            beta2, eps, step);
-    k_step_inc<<<1, 1, 0, st>>>(step);
+    k_adam<<<(unsigned)(n > 0 ? (n + 255) / 256 : 1), 256, 0, st>>>(
+        params, grad, m, v, n, lr, beta1, beta2, eps, step, (unsigned int *)(step + 1));
     return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP;
 }

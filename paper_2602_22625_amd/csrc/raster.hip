@@ -94,22 +94,25 @@ k_raster_fwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
              const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
-             float *__restrict__ saveT, const int *__restrict__ flags)
+             float *__restrict__ saveT, const int *__restrict__ flags,
+             unsigned long long *__restrict__ pair_counter)
 {
     if (flags[F_OVERFLOW]) return;
     const int tile = xcd_remap(blockIdx.x, n_tiles);
     const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
     const double xd = tg.px, yd = tg.py;
     const uint64_t vmask = __ballot(tg.valid);
-    const int start = tile_start[tile], n = tile_count[tile];
+    const int start = tile_start[tile], n = tile_count[(size_t)tile * CNT_STRIDE];
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, TK = 1.f;
     int K = -1;
+    unsigned long long npairs = 0;  // wave-uniform count of evaluated (pixel, primitive) pairs
     for (int j = 0; j < n; ++j) {
         const PrimRec &r = recs[pairs[start + j]];
         const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
         const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
         const uint64_t m = support_mask(r, U, V, vmask);
         if (m == 0) continue;  // no lane of this wave touches the primitive
+        npairs += __popcll(m);
         const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
         if (in) {
             float M, MU, MV;
@@ -123,6 +126,10 @@ k_raster_fwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
             T = T * (1.f - a);
         }
     }
+    if ((threadIdx.x & 63) == 0 && npairs)  // spread over slots: no single hot address
+        atomicAdd(pair_counter + ((blockIdx.x * (TS * TS / 64) + (threadIdx.x >> 6)) &
+                                  (DBMP_COUNTER_SLOTS - 1)),
+                  npairs);
     if (!tg.valid) return;
     const ImgDev &D = tg.D;
     const size_t plane = (size_t)D.H * D.W;
@@ -206,7 +213,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
         TK = saveT[gp];
     }
     float Bk = 1.f, Trun = TK;
-    const int start = tile_start[tile], n = tile_count[tile];
+    const int start = tile_start[tile], n = tile_count[(size_t)tile * CNT_STRIDE];
     for (int j = n - 1; j >= 0; --j) {
         const int g = pairs[start + j];
         const PrimRec &r = recs[g];
@@ -273,7 +280,8 @@ static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
     k_raster_fwd<TS, TexT, BGPP><<<a.n_tiles, TS * TS, 0, st>>>(
         a.recs, a.pairs, a.tile_start, a.tile_count, a.imgs, a.n_images, a.n_tiles,
-        (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK, a.saveT, a.flags);
+        (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK, a.saveT, a.flags,
+        a.pair_counter);
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA>
