@@ -57,22 +57,35 @@ typedef enum {
 typedef enum { DBMP_F32 = 0, DBMP_BF16 = 1 } dbmp_dtype;
 
 /* Creates a context on HIP device `device`. The context owns the workspace (per-primitive
- * records, tile lists, the padded atlas and the per-pixel state the backward needs) and grows
- * it on demand. `pair_capacity` is the initial size of the (tile, primitive) pair buffer in
- * entries (0 = a default of 2^20). Synchronous. */
-int dbmp_create(dbmp_ctx **out, int device, long long pair_capacity);
+ * records, the per-tile primitive lists, the padded atlas and the per-pixel state the backward
+ * needs) and grows it on demand. Every screen tile gets a list of `list_capacity` entries
+ * (0 = a default of 256); a forward in which some tile is overlapped by more primitives raises
+ * DBMP_EOVERFLOW (dbmp_check) and renders nothing. Synchronous. */
+int dbmp_create(dbmp_ctx **out, int device, long long list_capacity);
 
 /* Releases the context and its workspace. Synchronises the device first. */
 int dbmp_destroy(dbmp_ctx *ctx);
 
-/* Grows the pair buffer to at least `pair_capacity` entries (never shrinks). Synchronous. Use
- * after dbmp_check() returned DBMP_EOVERFLOW, with dbmp_pair_count() as the size. */
-int dbmp_reserve(dbmp_ctx *ctx, long long pair_capacity);
+/* Raises the per-tile list capacity to at least `list_capacity` entries (never lowers it; the
+ * memory grows at the next forward) and restarts the dbmp_longest_list statistic. Synchronous.
+ * Use after dbmp_check() returned DBMP_EOVERFLOW, with dbmp_longest_list() as the size. */
+int dbmp_reserve(dbmp_ctx *ctx, long long list_capacity);
+
+/*
+ * Stores the bitmap templates in the context: each bitmap is copied with a one-texel zero border
+ * (the zero padding of the bilinear sampler) and its bounding box of non-zero texels is found.
+ * Renders given atlas == NULL use this copy, so a fit loop pays for it once. A render given an
+ * atlas replaces it. Asynchronous on `stream`; the caller's atlas may be freed once the work on
+ * `stream` has finished.
+ */
+int dbmp_set_atlas(dbmp_ctx *ctx, dbmp_stream stream, const void *atlas, int B, int Hb, int Wb,
+                   int atlas_dtype);
 
 /*
  * Forward render of one image (Eqs. 1-5 with background), Sec. 3.1.1.
  *   params, atlas_idx, N      primitives (see conventions); N >= 0 (N = 0 gives I = b, A = 0).
- *   atlas, B, Hb, Wb, dtype   bitmap templates.
+ *   atlas, B, Hb, Wb, dtype   bitmap templates, or atlas = NULL to use the context's atlas (set
+ *                             by dbmp_set_atlas or a previous render; B, Hb, Wb, dtype ignored).
  *   H, W                      canvas size, >= 1.
  *   bg                        device float32: 3 values, or [3, H, W] when bg_per_pixel != 0.
  *   alpha_max                 in (0, 1] (Eq. 3).
@@ -99,6 +112,26 @@ int dbmp_render_backward(dbmp_ctx *ctx, dbmp_stream stream, const float *dL_dima
                          const float *dL_dalpha, float *dL_dparams);
 
 /*
+ * Backward of the last forward for the loss L = mean((I - target)^2) over each image's 3HW values
+ * (the `mse` loss of Supp. Table S1) plus any dL/dA: identical to dbmp_render_backward with
+ * dL/dI = 2 (I - target) / (3 H W), but the gradient is formed inside the backward from the
+ * forward's image instead of being read from a separate buffer.
+ *   target      device float32, laid out like the forward's image.
+ *   dL_dalpha   device float32 like the forward's alpha, or NULL.
+ *   dL_dparams  out, device float32 [rows, 8], overwritten.
+ *   accumulate  0: dL_dparams is overwritten; 1: the gradient is ADDED to dL_dparams (a fit
+ *               loop whose optimiser zeroes the gradient after use saves a clearing pass).
+ * The image passed to the forward must be unchanged. The squared errors are kept per tile for
+ * dbmp_mse_loss. Returns DBMP_ESTATE if no forward has run on this context.
+ */
+int dbmp_render_backward_mse(dbmp_ctx *ctx, dbmp_stream stream, const float *target,
+                             const float *dL_dalpha, float *dL_dparams, int accumulate);
+
+/* Sum over pixels and channels of (I - target)^2 of each image of the last
+ * dbmp_render_backward_mse, written to out[0 .. n_images) (device float32). Asynchronous. */
+int dbmp_mse_loss(dbmp_ctx *ctx, dbmp_stream stream, float *out);
+
+/*
  * Batched forward: n_images independent images rendered by one persistent launch per stage.
  * Image i has desc[i] = {H, W, N, prim_offset, pixel_offset}: its primitives are rows
  * [prim_offset, prim_offset + N) of params / atlas_idx, its image occupies
@@ -119,14 +152,15 @@ int dbmp_render_batched(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
                         float *image, float *alpha);
 
 /* Synchronises `stream` and reports the device-side errors raised by any forward since the
- * previous dbmp_check: DBMP_EOVERFLOW (a forward needed more pairs than the buffer holds; its
- * image is not valid), DBMP_EINVAL (atlas index out of range), DBMP_ENONFINITE, or DBMP_OK.
- * The reported errors are cleared. */
+ * previous dbmp_check: DBMP_EOVERFLOW (a tile list did not fit; that forward's image is not
+ * valid), DBMP_EINVAL (atlas index out of range), DBMP_ENONFINITE, or DBMP_OK. The reported
+ * errors are cleared. */
 int dbmp_check(dbmp_ctx *ctx, dbmp_stream stream);
 
-/* Largest number of (tile, primitive) pairs any forward needed since the last dbmp_reserve (or
- * dbmp_create): the size to pass to dbmp_reserve after DBMP_EOVERFLOW. Synchronises `stream`. */
-long long dbmp_pair_count(dbmp_ctx *ctx, dbmp_stream stream);
+/* Longest tile list (number of primitives overlapping one screen tile) of all forwards since
+ * the last dbmp_reserve (or dbmp_create): the capacity to pass to dbmp_reserve after
+ * DBMP_EOVERFLOW. Synchronises `stream`. */
+long long dbmp_longest_list(dbmp_ctx *ctx, dbmp_stream stream);
 
 /* Number of (pixel, primitive) pairs evaluated by all forwards on this context since it was
  * created or last reset: pairs where the primitive's bilinear footprint at the pixel reads at
@@ -152,9 +186,11 @@ int dbmp_mse_grad(dbmp_stream stream, const float *image, const float *target, l
  * points to TWO device int32: step[0] counts the steps already taken and step[1] is scratch for
  * the kernel; both must be zero before the first step. The call uses t = step[0] + 1 for the
  * bias correction and advances step[0] on the device, so it can be replayed from a graph.
+ * zero_grad != 0 sets grad to zero after reading it (for an accumulating backward).
  */
-int dbmp_adam_step(dbmp_stream stream, float *params, const float *grad, float *m, float *v,
-                   long long n, float lr, float beta1, float beta2, float eps, int32_t *step);
+int dbmp_adam_step(dbmp_stream stream, float *params, float *grad, float *m, float *v,
+                   long long n, float lr, float beta1, float beta2, float eps, int32_t *step,
+                   int zero_grad);
 
 #ifdef __cplusplus
 }

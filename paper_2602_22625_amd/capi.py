@@ -50,15 +50,18 @@ def load():
         "dbmp_create": ([ctypes.POINTER(P), I, LL], I),
         "dbmp_destroy": ([P], I),
         "dbmp_reserve": ([P, LL], I),
+        "dbmp_set_atlas": ([P, P, P, I, I, I, I], I),
         "dbmp_render": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P], I),
         "dbmp_render_backward": ([P, P, P, P, P], I),
+        "dbmp_render_backward_mse": ([P, P, P, P, P, I], I),
+        "dbmp_mse_loss": ([P, P, P], I),
         "dbmp_render_batched": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P], I),
         "dbmp_check": ([P, P], I),
-        "dbmp_pair_count": ([P, P], LL),
+        "dbmp_longest_list": ([P, P], LL),
         "dbmp_support_pairs": ([P, P, I], LL),
         "dbmp_last_error": ([P], ctypes.c_char_p),
         "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
-        "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P], I),
+        "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P, I], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -93,9 +96,9 @@ def _chk(ctx, rc):
 # ------------------------------------------------------------------------------------------
 # Same-name wrappers
 # ------------------------------------------------------------------------------------------
-def dbmp_create(device=0, pair_capacity=0):
+def dbmp_create(device=0, list_capacity=0):
     h = ctypes.c_void_p()
-    _chk(None, load().dbmp_create(ctypes.byref(h), int(device), int(pair_capacity)))
+    _chk(None, load().dbmp_create(ctypes.byref(h), int(device), int(list_capacity)))
     return h.value
 
 
@@ -103,8 +106,13 @@ def dbmp_destroy(ctx):
     return _chk(None, load().dbmp_destroy(ctx))
 
 
-def dbmp_reserve(ctx, pair_capacity):
-    return _chk(ctx, load().dbmp_reserve(ctx, int(pair_capacity)))
+def dbmp_reserve(ctx, list_capacity):
+    return _chk(ctx, load().dbmp_reserve(ctx, int(list_capacity)))
+
+
+def dbmp_set_atlas(ctx, stream, atlas, B, Hb, Wb, atlas_dtype):
+    return _chk(ctx, load().dbmp_set_atlas(ctx, stream, ptr(atlas), int(B), int(Hb), int(Wb),
+                                           int(atlas_dtype)))
 
 
 def dbmp_render(ctx, stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dtype, H, W, bg,
@@ -118,6 +126,15 @@ def dbmp_render(ctx, stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dtype
 def dbmp_render_backward(ctx, stream, dL_dimage, dL_dalpha, dL_dparams):
     return _chk(ctx, load().dbmp_render_backward(ctx, stream, ptr(dL_dimage), ptr(dL_dalpha),
                                                  ptr(dL_dparams)))
+
+
+def dbmp_render_backward_mse(ctx, stream, target, dL_dalpha, dL_dparams, accumulate=0):
+    return _chk(ctx, load().dbmp_render_backward_mse(ctx, stream, ptr(target), ptr(dL_dalpha),
+                                                     ptr(dL_dparams), int(accumulate)))
+
+
+def dbmp_mse_loss(ctx, stream, out):
+    return _chk(ctx, load().dbmp_mse_loss(ctx, stream, ptr(out)))
 
 
 def dbmp_render_batched(ctx, stream, descs, params, atlas_idx, atlas, B, Hb, Wb, atlas_dtype,
@@ -135,8 +152,8 @@ def dbmp_check(ctx, stream):
     return load().dbmp_check(ctx, stream)
 
 
-def dbmp_pair_count(ctx, stream):
-    return int(load().dbmp_pair_count(ctx, stream))
+def dbmp_longest_list(ctx, stream):
+    return int(load().dbmp_longest_list(ctx, stream))
 
 
 def dbmp_support_pairs(ctx, stream, reset=0):
@@ -152,7 +169,7 @@ def dbmp_mse_grad(stream, image, target, n, grad, loss):
                                            ptr(loss)))
 
 
-def dbmp_adam_step(stream, params, grad, m, v, n, lr, beta1, beta2, eps, step):
+def dbmp_adam_step(stream, params, grad, m, v, n, lr, beta1, beta2, eps, step, zero_grad=0):
     return _chk(None, load().dbmp_adam_step(stream, ptr(params), ptr(grad), ptr(m), ptr(v),
                                             int(n), float(lr), float(beta1), float(beta2),
-                                            float(eps), ptr(step)))
+                                            float(eps), ptr(step), int(zero_grad)))

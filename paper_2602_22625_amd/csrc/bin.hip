@@ -3,14 +3,16 @@
 //
 // Stages, all on the device and all asynchronous:
 //   k_setup    pads every bitmap with a one-texel zero border (the zero padding of the bilinear
-//              sampler), finds each bitmap's tight non-zero box, clears counters and flags;
+//              sampler) and finds each bitmap's tight non-zero box (once per atlas);
 //   k_prep     per primitive: sigmoid/exp/sincos, the inverse affine map of Eqs. (1)-(2) folded
-//              into U' = aU x + bU y + eU (float64), the exact support parallelogram, its tile
-//              span, and a count per overlapped tile (separating-axis test, so rotated
-//              primitives are not charged for the corners of their bounding box);
-//   k_scan     exclusive scan of the per-tile counts -> per-tile list starts, overflow check;
-//   k_emit     writes primitive ids into their tiles' lists (order within a tile arbitrary);
-//   k_sort     sorts every tile's list ascending = front to back (depth order = index order).
+//              into U' = aU x + bU y + eU (float64), the exact support parallelogram and its
+//              tile span; then sixteen lanes per primitive walk the span, test each tile (a
+//              separating-axis test, so rotated primitives are not charged for the corners of
+//              their bounding box) and append the primitive's row to the tile's list.
+// Every tile owns a list of fixed capacity (lists[t * cap .. ]), so appending needs one atomic
+// per (tile, primitive) pair and no prefix scan or second pass; a tile whose list would
+// overflow raises a flag and the caller grows the capacity. The forward raster kernel sorts
+// each tile's list front to back (depth order = index order).
 #include "dbmp_internal.h"
 
 #include <limits.h>
@@ -26,10 +28,10 @@ namespace dbmp {
 template <typename TexT>
 __global__ void __launch_bounds__(SETUP_THREADS)
 k_setup(const TexT *__restrict__ atlas, int B, int Hb, int Wb, TexT *__restrict__ pad, int Wp,
-        int *__restrict__ box, int *__restrict__ tile_count, int n_tiles, int *__restrict__ flags)
+        int *__restrict__ box)
 {
     const int Hp = Hb + 2;
-    if ((int)blockIdx.x < B) {
+    {
         const int b = blockIdx.x;
         const TexT *src = atlas + (size_t)b * Hb * Wb;
         TexT *dst = pad + (size_t)b * Hp * Wp;
@@ -81,11 +83,6 @@ k_setup(const TexT *__restrict__ atlas, int B, int Hb, int Wb, TexT *__restrict_
             box[4 * b + 0] = s[4] ? INT_MIN : s[0]; box[4 * b + 1] = s[1];
             box[4 * b + 2] = s[2]; box[4 * b + 3] = s[3];
         }
-    } else {
-        const int nb = gridDim.x - B, ib = blockIdx.x - B;
-        for (int i = ib * blockDim.x + threadIdx.x; i < n_tiles; i += nb * blockDim.x)
-            tile_count[(size_t)i * CNT_STRIDE] = 0;
-        if (ib == 0 && threadIdx.x < F_S_OVERFLOW) flags[threadIdx.x] = 0;  // per-forward flags
     }
 }
 
@@ -95,7 +92,8 @@ k_setup(const TexT *__restrict__ atlas, int B, int Hb, int Wb, TexT *__restrict_
 // tile's own axes are covered by the bounding-box span. The margin keeps the test conservative
 // against rounding; the raster kernels test every pixel exactly.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ bool tile_hits(const PrimRec &r, int X0, int X1, int Y0, int Y1)
+template <typename R>
+__device__ __forceinline__ bool tile_hits(const R &r, int X0, int X1, int Y0, int Y1)
 {
     const double m = 1e-6;
     const double ux0 = r.aU * X0, ux1 = r.aU * X1, uy0 = r.bU * Y0, uy1 = r.bU * Y1;
@@ -110,321 +108,173 @@ __device__ __forceinline__ bool tile_hits(const PrimRec &r, int X0, int X1, int 
 }
 
 // ------------------------------------------------------------------------------------------
-// k_prep: one thread per (global) primitive row.
+// k_prep
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+#define PREP_THREADS 1024
+#define PREP_PRIMS 64    // primitives per workgroup: one wave computes records, all walk tiles
+#define TILE_LANES 16
+
+// The fields of a record the tile walk needs, kept in LDS between the two phases of k_prep.
+struct WalkRec {
+    double aU, bU, eU, aV, bV, eV, Ulo, Uhi, Vlo, Vhi;
+    int tx0, tx1, ty0, ty1, tile_off, ntx, W, H;
+};
+
+__global__ void __launch_bounds__(PREP_THREADS)
 k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long n_rows,
        const ImgDev *__restrict__ imgs, int n_images, const int *__restrict__ box, int B, int Hb,
        int Wb, int Wp, float alpha_max, int TS, PrimRec *__restrict__ recs,
-       int *__restrict__ tile_count, int *__restrict__ flags)
+       int *__restrict__ tile_count, int *__restrict__ lists, int list_cap,
+       int *__restrict__ flags)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_rows) return;
-    PrimRec rec;
-    rec.aU = rec.bU = rec.eU = rec.aV = rec.bV = rec.eV = 0.0;
-    rec.Ulo = 1.0; rec.Uhi = 0.0; rec.Vlo = 1.0; rec.Vhi = 0.0;  // empty support
-    rec.ka = 0.f; rec.cr = rec.cg = rec.cb = 0.f; rec.tex = 0; rec.omsig = 1.f;
-    rec.faU = rec.fbU = rec.faV = rec.fbV = 0.f;
-    rec.tx0 = 1; rec.tx1 = 0; rec.ty0 = 1; rec.ty1 = 0;
-    rec.pad[0] = rec.pad[1] = rec.pad[2] = 0;
-    const int b = find_by_prim(imgs, n_images, g);
-    const ImgDev D = imgs[b];
-    rec.img = b;
-    const bool in_image = g >= D.prim_off && g < D.prim_off + D.N;
-    if (in_image) {
-        float p[8];
+    __shared__ WalkRec s_rec[PREP_PRIMS];
+    if (threadIdx.x < PREP_PRIMS) {
+        const long long g = (long long)blockIdx.x * PREP_PRIMS + threadIdx.x;
+        PrimRec rec;
+        rec.aU = rec.bU = rec.eU = rec.aV = rec.bV = rec.eV = 0.0;
+        rec.Ulo = 1.0; rec.Uhi = 0.0; rec.Vlo = 1.0; rec.Vhi = 0.0;  // empty support
+        rec.ka = 0.f; rec.cr = rec.cg = rec.cb = 0.f; rec.tex = 0; rec.kaom = 0.f;
+        rec.ccr = rec.ccg = rec.ccb = 0.f;
+        rec.faU = rec.fbU = rec.faV = rec.fbV = 0.f;
+        rec.tx0 = 1; rec.tx1 = 0; rec.ty0 = 1; rec.ty1 = 0;
+        rec.img = rec.tile_off = rec.ntx = rec.W = rec.H = 0;
+        rec.pad[0] = rec.pad[1] = 0;
+        if (g < n_rows) {
+            const int b = find_by_prim(imgs, n_images, g);
+            const ImgDev D = imgs[b];
+            rec.img = b; rec.tile_off = D.tile_off; rec.ntx = D.ntx; rec.W = D.W; rec.H = D.H;
+            if (g >= D.prim_off && g < D.prim_off + D.N) {
+                float p[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
-        const int k = idx[g];
-        bool ok = true;
-        if (k < 0 || k >= B) {
-            atomicOr(&flags[F_BADIDX], 1);
-            atomicOr(&flags[F_S_BADIDX], 1);
-            ok = false;
-        }
-        bool fin = true;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) fin = fin && isfinite(p[j]);
-        const double s = exp((double)p[2]);
-        if (!(s > 0.0) || !isfinite(s)) fin = false;  // scale underflows or overflows
-        if (!fin) {
-            atomicOr(&flags[F_NONFINITE], 1);
-            atomicOr(&flags[F_S_NONFINITE], 1);
-            ok = false;
-        }
-        if (ok) {
-            double st, ct;
-            sincos((double)p[3], &st, &ct);
-            const double inv_s = 1.0 / s;
-            const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1);  // dU/du, dV/dv of Eq. (2)
-            const double x = p[0], y = p[1];
-            // Eq. (1)-(2): u = (ct dx + st dy)/s, v = (-st dx + ct dy)/s, U = cu (u + 1), plus the
-            // one-texel shift into the padded bitmap.
-            rec.aU = cu * ct * inv_s;  rec.bU = cu * st * inv_s;
-            rec.aV = -cv * st * inv_s; rec.bV = cv * ct * inv_s;
-            rec.eU = (cu + 1.0) - rec.aU * x - rec.bU * y;
-            rec.eV = (cv + 1.0) - rec.aV * x - rec.bV * y;
-            rec.faU = (float)rec.aU; rec.fbU = (float)rec.bU;
-            rec.faV = (float)rec.aV; rec.fbV = (float)rec.bV;
-            const double sig = 1.0 / (1.0 + exp(-(double)p[4]));
-            rec.ka = (float)(alpha_max * sig);
-            rec.omsig = (float)(1.0 / (1.0 + exp((double)p[4])));  // 1 - sigmoid, no cancellation
-            rec.cr = (float)(1.0 / (1.0 + exp(-(double)p[5])));
-            rec.cg = (float)(1.0 / (1.0 + exp(-(double)p[6])));
-            rec.cb = (float)(1.0 / (1.0 + exp(-(double)p[7])));
-            const int Hp = Hb + 2;
-            rec.tex = k * Hp * Wp;
-            int xlo = box[4 * k];
-            const int xhi = box[4 * k + 1];
-            const int ylo = box[4 * k + 2], yhi = box[4 * k + 3];
-            if (xlo == INT_MIN) {  // the bitmap holds a non-finite texel (read as 0)
-                atomicOr(&flags[F_NONFINITE], 1);
-                atomicOr(&flags[F_S_NONFINITE], 1);
-                xlo = 0;
-            }
-            if (xlo <= xhi && D.W > 0 && D.H > 0) {
-                // floor(U') in [xlo, xhi + 1] reads at least one non-zero texel (padded columns
-                // xlo + 1 .. xhi + 1); elsewhere M and its derivatives are exactly zero.
-                rec.Ulo = xlo; rec.Uhi = xhi + 2;
-                rec.Vlo = ylo; rec.Vhi = yhi + 2;
-                double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double Uc = (c & 1) ? rec.Uhi : rec.Ulo;
-                    const double Vc = (c & 2) ? rec.Vhi : rec.Vlo;
-                    const double u = (Uc - 1.0) / cu - 1.0, v = (Vc - 1.0) / cv - 1.0;
-                    const double X = x + s * (ct * u - st * v);
-                    const double Y = y + s * (st * u + ct * v);
-                    xmin = fmin(xmin, X); xmax = fmax(xmax, X);
-                    ymin = fmin(ymin, Y); ymax = fmax(ymax, Y);
+                for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
+                const int k = idx[g];
+                bool ok = true;
+                if (k < 0 || k >= B) {
+                    atomicOr(&flags[F_S_BADIDX], 1);
+                    ok = false;
                 }
-                const double mg = 1e-3;
-                const double fx0 = fmax(ceil(xmin - mg), 0.0), fx1 = fmin(floor(xmax + mg), D.W - 1.0);
-                const double fy0 = fmax(ceil(ymin - mg), 0.0), fy1 = fmin(floor(ymax + mg), D.H - 1.0);
-                if (fx0 <= fx1 && fy0 <= fy1) {
-                    rec.tx0 = (int)fx0 / TS; rec.tx1 = (int)fx1 / TS;
-                    rec.ty0 = (int)fy0 / TS; rec.ty1 = (int)fy1 / TS;
+                bool fin = true;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) fin = fin && isfinite(p[j]);
+                const double s = exp((double)p[2]);
+                if (!(s > 0.0) || !isfinite(s)) fin = false;  // scale underflows or overflows
+                if (!fin) {
+                    atomicOr(&flags[F_S_NONFINITE], 1);
+                    ok = false;
+                }
+                if (ok) {
+                    double st, ct;
+                    sincos((double)p[3], &st, &ct);
+                    const double inv_s = 1.0 / s;
+                    const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1);  // dU/du, dV/dv
+                    const double x = p[0], y = p[1];
+                    // Eq. (1)-(2): u = (ct dx + st dy)/s, v = (-st dx + ct dy)/s, U = cu (u + 1),
+                    // plus the one-texel shift into the padded bitmap.
+                    rec.aU = cu * ct * inv_s;  rec.bU = cu * st * inv_s;
+                    rec.aV = -cv * st * inv_s; rec.bV = cv * ct * inv_s;
+                    rec.eU = (cu + 1.0) - rec.aU * x - rec.bU * y;
+                    rec.eV = (cv + 1.0) - rec.aV * x - rec.bV * y;
+                    rec.faU = (float)rec.aU; rec.fbU = (float)rec.bU;
+                    rec.faV = (float)rec.aV; rec.fbV = (float)rec.bV;
+                    const double sig = 1.0 / (1.0 + exp(-(double)p[4]));
+                    const double omsig = 1.0 / (1.0 + exp((double)p[4]));  // 1 - sigmoid
+                    rec.ka = (float)(alpha_max * sig);
+                    rec.kaom = (float)(alpha_max * sig * omsig);
+                    double c3[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) c3[j] = 1.0 / (1.0 + exp(-(double)p[5 + j]));
+                    rec.cr = (float)c3[0]; rec.cg = (float)c3[1]; rec.cb = (float)c3[2];
+                    rec.ccr = (float)(c3[0] / (1.0 + exp((double)p[5])));  // c (1 - c)
+                    rec.ccg = (float)(c3[1] / (1.0 + exp((double)p[6])));
+                    rec.ccb = (float)(c3[2] / (1.0 + exp((double)p[7])));
+                    const int Hp = Hb + 2;
+                    rec.tex = k * Hp * Wp;
+                    int xlo = box[4 * k];
+                    const int xhi = box[4 * k + 1];
+                    const int ylo = box[4 * k + 2], yhi = box[4 * k + 3];
+                    if (xlo == INT_MIN) {  // the bitmap holds a non-finite texel (read as 0)
+                        atomicOr(&flags[F_S_NONFINITE], 1);
+                        xlo = 0;
+                    }
+                    if (xlo <= xhi) {
+                        // floor(U') in [xlo, xhi + 1] reads at least one non-zero texel (padded
+                        // columns xlo + 1 .. xhi + 1); elsewhere M and its derivatives are 0.
+                        rec.Ulo = xlo; rec.Uhi = xhi + 2;
+                        rec.Vlo = ylo; rec.Vhi = yhi + 2;
+                        double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const double Uc = (c & 1) ? rec.Uhi : rec.Ulo;
+                            const double Vc = (c & 2) ? rec.Vhi : rec.Vlo;
+                            const double u = (Uc - 1.0) / cu - 1.0, v = (Vc - 1.0) / cv - 1.0;
+                            const double X = x + s * (ct * u - st * v);
+                            const double Y = y + s * (st * u + ct * v);
+                            xmin = fmin(xmin, X); xmax = fmax(xmax, X);
+                            ymin = fmin(ymin, Y); ymax = fmax(ymax, Y);
+                        }
+                        const double mg = 1e-3;
+                        const double fx0 = fmax(ceil(xmin - mg), 0.0);
+                        const double fx1 = fmin(floor(xmax + mg), D.W - 1.0);
+                        const double fy0 = fmax(ceil(ymin - mg), 0.0);
+                        const double fy1 = fmin(floor(ymax + mg), D.H - 1.0);
+                        if (fx0 <= fx1 && fy0 <= fy1) {
+                            rec.tx0 = (int)fx0 / TS; rec.tx1 = (int)fx1 / TS;
+                            rec.ty0 = (int)fy0 / TS; rec.ty1 = (int)fy1 / TS;
+                        }
+                    }
                 }
             }
+            recs[g] = rec;
         }
+        WalkRec &wr = s_rec[threadIdx.x];
+        wr.aU = rec.aU; wr.bU = rec.bU; wr.eU = rec.eU; wr.aV = rec.aV; wr.bV = rec.bV;
+        wr.eV = rec.eV; wr.Ulo = rec.Ulo; wr.Uhi = rec.Uhi; wr.Vlo = rec.Vlo; wr.Vhi = rec.Vhi;
+        wr.tx0 = rec.tx0; wr.tx1 = rec.tx1; wr.ty0 = rec.ty0; wr.ty1 = rec.ty1;
+        wr.tile_off = rec.tile_off; wr.ntx = rec.ntx; wr.W = rec.W; wr.H = rec.H;
     }
-    recs[g] = rec;
-}
-
-// k_count: 16 lanes per primitive walk its tile span and count the tiles its support hits.
-__global__ void __launch_bounds__(256)
-k_count(const PrimRec *__restrict__ recs, long long n_rows, const ImgDev *__restrict__ imgs,
-        int TS, int *__restrict__ tile_count)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long g = t / 16;
-    const int l = (int)(t % 16);
-    if (g >= n_rows) return;
-    const PrimRec &r = recs[g];
-    if (r.tx0 > r.tx1) return;
-    const ImgDev D = imgs[r.img];
-    const int nx = r.tx1 - r.tx0 + 1, ny = r.ty1 - r.ty0 + 1;
-    for (int k = l; k < nx * ny; k += 16) {
-        const int tx = r.tx0 + k % nx, ty = r.ty0 + k / nx;
-        const int X0 = tx * TS, X1 = min(X0 + TS - 1, D.W - 1);
-        const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, D.H - 1);
-        if (tile_hits(r, X0, X1, Y0, Y1))
-            atomicAdd(&tile_count[(size_t)(D.tile_off + ty * D.ntx + tx) * CNT_STRIDE], 1);
-    }
-}
-
-// ------------------------------------------------------------------------------------------
-// k_scan: one workgroup of 1024 threads; exclusive scan of tile_count into tile_start, then
-// tile_count is zeroed to serve as the fill counter of k_emit (which restores it).
-// ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-k_scan(int *__restrict__ tile_count, int *__restrict__ tile_start, int n_tiles,
-       long long pair_cap, int *__restrict__ flags)
-{
-    constexpr int PER = 4;
-    __shared__ long long wsum[16];
-    __shared__ long long carry_s;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    if (t == 0) carry_s = 0;
     __syncthreads();
-    for (int base = 0; base < n_tiles; base += 1024 * PER) {
-        int v[PER];
-        long long loc = 0;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int j = base + t * PER + i;
-            v[i] = j < n_tiles ? tile_count[(size_t)j * CNT_STRIDE] : 0;
-            loc += v[i];
-        }
-        // inclusive wave scan of loc
-        long long inc = loc;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const long long o = __shfl_up(inc, d);
-            if (lane >= d) inc += o;
-        }
-        if (lane == 63) wsum[w] = inc;
-        __syncthreads();
-        long long wpre = 0;
-        for (int i = 0; i < w; ++i) wpre += wsum[i];
-        long long run = carry_s + wpre + inc - loc;  // exclusive prefix of this thread
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int j = base + t * PER + i;
-            if (j < n_tiles) {
-                tile_start[j] = (int)(run < INT_MAX ? run : INT_MAX);
-                tile_count[(size_t)j * CNT_STRIDE] = 0;
+    // Sixteen lanes per primitive walk its tile span and append it to every tile it hits.
+    const int lane = threadIdx.x % TILE_LANES;
+    for (int q = 0; q < PREP_PRIMS * TILE_LANES / PREP_THREADS; ++q) {
+        const int pl = q * (PREP_THREADS / TILE_LANES) + (int)threadIdx.x / TILE_LANES;
+        const WalkRec &r = s_rec[pl];
+        if (r.tx0 > r.tx1) continue;
+        const int g = (int)((long long)blockIdx.x * PREP_PRIMS + pl);
+        const int nx = r.tx1 - r.tx0 + 1, ny = r.ty1 - r.ty0 + 1;
+        for (int k = lane; k < nx * ny; k += TILE_LANES) {
+            const int tx = r.tx0 + k % nx, ty = r.ty0 + k / nx;
+            const int X0 = tx * TS, X1 = min(X0 + TS - 1, r.W - 1);
+            const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, r.H - 1);
+            if (!tile_hits(r, X0, X1, Y0, Y1)) continue;
+            const int tt = r.tile_off + ty * r.ntx + tx;
+            const int pos = atomicAdd(&tile_count[tt], 1);
+            if (pos < list_cap) {
+                lists[(size_t)tt * list_cap + pos] = g;
+            } else if (pos == list_cap) {  // the first entry that does not fit
+                flags[F_S_OVERFLOW] = 1;
             }
-            run += v[i];
-        }
-        __syncthreads();
-        if (t == 1023) carry_s = run;
-        __syncthreads();
-    }
-    if (t == 0) {
-        const long long total = carry_s;
-        const int tc = (int)(total < INT_MAX ? total : INT_MAX);
-        flags[F_TOTAL] = tc;
-        atomicMax(&flags[F_S_TOTALMAX], tc);
-        if (total > pair_cap) {
-            flags[F_OVERFLOW] = 1;
-            flags[F_S_OVERFLOW] = 1;
         }
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// k_emit: appends each primitive's row to the lists of the tiles it hits. Sixteen lanes share
-// a primitive and split its tile span, so its (returning) atomics are issued together instead
-// of one after another.
+// Host launcher
 // ------------------------------------------------------------------------------------------
-#define EMIT_LANES 16
-
-__global__ void __launch_bounds__(256)
-k_emit(const PrimRec *__restrict__ recs, long long n_rows, const ImgDev *__restrict__ imgs, int TS,
-       const int *__restrict__ tile_start, int *__restrict__ tile_fill, int *__restrict__ pairs,
-       long long pair_cap)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long g = t / EMIT_LANES;
-    const int l = (int)(t % EMIT_LANES);
-    if (g >= n_rows) return;
-    const PrimRec &r = recs[g];
-    if (r.tx0 > r.tx1) return;
-    const ImgDev D = imgs[r.img];
-    const int nx = r.tx1 - r.tx0 + 1, ny = r.ty1 - r.ty0 + 1;
-    for (int k = l; k < nx * ny; k += EMIT_LANES) {
-        const int tx = r.tx0 + k % nx, ty = r.ty0 + k / nx;
-        const int X0 = tx * TS, X1 = min(X0 + TS - 1, D.W - 1);
-        const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, D.H - 1);
-        if (!tile_hits(r, X0, X1, Y0, Y1)) continue;
-        const int tt = D.tile_off + ty * D.ntx + tx;
-        const long long pos =
-            (long long)tile_start[tt] + atomicAdd(&tile_fill[(size_t)tt * CNT_STRIDE], 1);
-        if (pos < pair_cap) pairs[pos] = (int)g;
-    }
-}
-
-// ------------------------------------------------------------------------------------------
-// k_sort: one wave per tile, ascending order (front to back). Lists of up to 64 entries are
-// ranked in registers; up to SORT_LDS entries are sorted in LDS; longer lists in place in global
-// memory. The bitonic network uses only ascending comparators (the first sub-stage of every
-// merge compares i with i ^ (k - 1)), so a list of any length n behaves as if padded with +inf
-// and comparators reaching past n are skipped.
-// ------------------------------------------------------------------------------------------
-#define SORT_LDS 2048
-
-template <typename Buf>
-__device__ __forceinline__ void bitonic_asc(Buf &a, int n, int lane)
-{
-    int N2 = 1;
-    while (N2 < n) N2 <<= 1;
-    for (int k = 2; k <= N2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < N2; i += 64) {
-                const int l = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
-                if (l > i && l < n) {
-                    const int x = a.get(i), y = a.get(l);
-                    if (y < x) { a.set(i, y); a.set(l, x); }
-                }
-            }
-            a.sync();
-        }
-    }
-}
-
-struct LdsBuf {
-    int *p;
-    __device__ int get(int i) const { return p[i]; }
-    __device__ void set(int i, int v) { p[i] = v; }
-    __device__ void sync() { __syncthreads(); }
-};
-struct GlobalBuf {  // one wave on one CU: volatile loads read through to L2
-    int *p;
-    __device__ int get(int i) const { return ((volatile int *)p)[i]; }
-    __device__ void set(int i, int v) { ((volatile int *)p)[i] = v; }
-    __device__ void sync() { __threadfence_block(); __syncthreads(); }
-};
-
-__global__ void __launch_bounds__(64)
-k_sort(int *__restrict__ pairs, const int *__restrict__ tile_start,
-       const int *__restrict__ tile_count, int n_tiles, const int *__restrict__ flags)
-{
-    if (flags[F_OVERFLOW]) return;
-    const int t = blockIdx.x;
-    if (t >= n_tiles) return;
-    const int lane = threadIdx.x;
-    const int n = tile_count[(size_t)t * CNT_STRIDE];
-    if (n <= 1) return;
-    int *seg = pairs + tile_start[t];
-    if (n <= 64) {
-        const int v = lane < n ? seg[lane] : INT_MAX;
-        int rank = 0;
-        for (int k = 0; k < n; ++k) rank += (__shfl(v, k) < v);
-        if (lane < n) seg[rank] = v;
-        return;
-    }
-    if (n <= SORT_LDS) {
-        __shared__ int buf[SORT_LDS];
-        for (int i = lane; i < n; i += 64) buf[i] = seg[i];
-        __syncthreads();
-        LdsBuf b{buf};
-        bitonic_asc(b, n, lane);
-        for (int i = lane; i < n; i += 64) seg[i] = buf[i];
-        return;
-    }
-    GlobalBuf gb{seg};
-    bitonic_asc(gb, n, lane);
-}
-
-// ------------------------------------------------------------------------------------------
-// Host launchers
-// ------------------------------------------------------------------------------------------
-
 hipError_t launch_binning(const BinArgs &a, hipStream_t st)
 {
-    const int zb = a.n_tiles > 0 ? min((a.n_tiles + SETUP_THREADS - 1) / SETUP_THREADS, 256) : 1;
-    if (a.dtype == 0)
-        k_setup<float><<<a.B + zb, SETUP_THREADS, 0, st>>>((const float *)a.atlas, a.B, a.Hb, a.Wb,
-                                                  (float *)a.atlas_pad, a.Wp, a.box, a.tile_count,
-                                                  a.n_tiles, a.flags);
-    else
-        k_setup<uint16_t><<<a.B + zb, SETUP_THREADS, 0, st>>>((const uint16_t *)a.atlas, a.B, a.Hb, a.Wb,
-                                                     (uint16_t *)a.atlas_pad, a.Wp, a.box,
-                                                     a.tile_count, a.n_tiles, a.flags);
+    if (a.pad_atlas) {
+        if (a.dtype == 0)
+            k_setup<float><<<a.B, SETUP_THREADS, 0, st>>>((const float *)a.atlas, a.B, a.Hb, a.Wb,
+                                                           (float *)a.atlas_pad, a.Wp, a.box);
+        else
+            k_setup<uint16_t><<<a.B, SETUP_THREADS, 0, st>>>((const uint16_t *)a.atlas, a.B, a.Hb,
+                                                              a.Wb, (uint16_t *)a.atlas_pad, a.Wp,
+                                                              a.box);
+    }
     if (a.n_rows > 0)
-        k_prep<<<(unsigned)((a.n_rows + 255) / 256), 256, 0, st>>>(
+        k_prep<<<(unsigned)((a.n_rows + PREP_PRIMS - 1) / PREP_PRIMS), PREP_THREADS, 0, st>>>(
             a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
-            a.alpha_max, a.TS, a.recs, a.tile_count, a.flags);
-    if (a.n_rows > 0)
-        k_count<<<(unsigned)((a.n_rows * 16 + 255) / 256), 256, 0, st>>>(a.recs, a.n_rows, a.imgs,
-                                                                          a.TS, a.tile_count);
-    k_scan<<<1, 1024, 0, st>>>(a.tile_count, a.tile_start, a.n_tiles, a.pair_cap, a.flags);
-    if (a.n_rows > 0)
-        k_emit<<<(unsigned)((a.n_rows * EMIT_LANES + 255) / 256), 256, 0, st>>>(
-            a.recs, a.n_rows, a.imgs, a.TS, a.tile_start, a.tile_count, a.pairs, a.pair_cap);
-    if (a.n_tiles > 0)
-        k_sort<<<a.n_tiles, 64, 0, st>>>(a.pairs, a.tile_start, a.tile_count, a.n_tiles, a.flags);
+            a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags);
     return hipGetLastError();
 }
 

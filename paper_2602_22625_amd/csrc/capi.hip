@@ -25,11 +25,16 @@ struct Buf {
 struct dbmp_ctx {
     int device = 0;
     std::string err;
-    Buf recs, tile_count, tile_start, pairs, saveK, saveT, atlas_pad, box, imgs, flags, counter;
-    long long pair_cap = 0;
+    Buf recs, tile_count, tile_len, lists, saveK, saveT, atlas_pad, box, imgs, flags, counter,
+        list_max, loss_tile;
+    int list_cap = 0;  // entries per tile list
+    // the padded atlas held in atlas_pad (set by dbmp_set_atlas or a render given an atlas)
+    bool atlas_valid = false;
+    int atlas_B = 0, atlas_Hb = 0, atlas_Wb = 0, atlas_dtype = 0;
     std::vector<ImgDev> imgs_uploaded;  // what the device copy of the descriptors holds
     // state of the last forward, for the backward
     bool have_fwd = false;
+    bool have_loss = false;
     RasterArgs ra{};
     long long n_rows = 0;
 };
@@ -105,22 +110,66 @@ bool same_imgs(const std::vector<ImgDev> &a, const std::vector<ImgDev> &b)
     return true;
 }
 
-// Shared body of dbmp_render and dbmp_render_batched.
+// Validates an atlas and pads it into the context (enqueued on st).
+int set_atlas_impl(dbmp_ctx *c, hipStream_t st, const void *atlas, int B, int Hb, int Wb,
+                   int dtype)
+{
+    if (!atlas || B < 1 || Hb < 2 || Wb < 2) return fail(c, DBMP_EINVAL, "bad atlas shape");
+    if (dtype != DBMP_F32 && dtype != DBMP_BF16) return fail(c, DBMP_EINVAL, "bad atlas dtype");
+    const int Hp = Hb + 2, Wp = Wb + 2;
+    if ((long long)B * Hp * Wp >= INT_MAX) return fail(c, DBMP_EINVAL, "atlas too large");
+    int rc;
+    const size_t esz = dtype == DBMP_F32 ? 4 : 2;
+    if ((rc = ensure(c, c->atlas_pad, esz * (size_t)B * Hp * Wp, st, "atlas"))) return rc;
+    if ((rc = ensure(c, c->box, 16 * (size_t)B, st, "boxes"))) return rc;
+    BinArgs ba{};
+    ba.atlas = atlas; ba.dtype = dtype; ba.B = B; ba.Hb = Hb; ba.Wb = Wb; ba.Wp = Wp;
+    ba.atlas_pad = c->atlas_pad.p; ba.box = (int *)c->box.p; ba.pad_atlas = true;
+    ba.n_rows = 0;
+    hipError_t e = launch_binning(ba, st);
+    if (e != hipSuccess) return hip_fail(c, e, "atlas launch");
+    c->atlas_valid = true;
+    c->atlas_B = B; c->atlas_Hb = Hb; c->atlas_Wb = Wb; c->atlas_dtype = dtype;
+    return DBMP_OK;
+}
+
+// Grows a counter buffer that must read as zero; new memory is cleared synchronously.
+int ensure_zeroed(dbmp_ctx *c, Buf &b, size_t bytes, hipStream_t st, const char *what)
+{
+    void *before = b.p;
+    int rc = ensure(c, b, bytes, st, what);
+    if (rc) return rc;
+    if (b.p != before) {
+        hipError_t e = hipMemset(b.p, 0, b.cap);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(c, e, "counter clear");
+    }
+    return DBMP_OK;
+}
+
+// Shared body of dbmp_render and dbmp_render_batched. atlas == NULL: the context's atlas.
 int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> &descs,
                 const float *params, const int32_t *atlas_idx, const void *atlas, int B, int Hb,
                 int Wb, int dtype, const float *bg, int bg_pp, float alpha_max, int tile,
                 float *image, float *alpha)
 {
-    if (!atlas || B < 1 || Hb < 2 || Wb < 2) return fail(c, DBMP_EINVAL, "bad atlas shape");
-    if (dtype != DBMP_F32 && dtype != DBMP_BF16) return fail(c, DBMP_EINVAL, "bad atlas dtype");
     if (!bg) return fail(c, DBMP_EINVAL, "bg is NULL");
     if (!(alpha_max > 0.f && alpha_max <= 1.f))
         return fail(c, DBMP_EINVAL, "alpha_max must be in (0, 1]");
     if (tile != 8 && tile != 16 && tile != 32)
         return fail(c, DBMP_EINVAL, "tile must be 8, 16 or 32");
     if (!image) return fail(c, DBMP_EINVAL, "image is NULL");
-    const int Hp = Hb + 2, Wp = Wb + 2;
-    if ((long long)B * Hp * Wp >= INT_MAX) return fail(c, DBMP_EINVAL, "atlas too large");
+    int rc;
+    if (atlas) {
+        if (capturing(st) && !(c->atlas_valid && B == c->atlas_B && Hb == c->atlas_Hb &&
+                               Wb == c->atlas_Wb && dtype == c->atlas_dtype))
+            return fail(c, DBMP_ESTATE, "atlas shape changed during graph capture");
+        if ((rc = set_atlas_impl(c, st, atlas, B, Hb, Wb, dtype))) return rc;
+    } else if (!c->atlas_valid) {
+        return fail(c, DBMP_EINVAL, "atlas is NULL and no atlas was set on this context");
+    }
+    B = c->atlas_B; Hb = c->atlas_Hb; Wb = c->atlas_Wb; dtype = c->atlas_dtype;
+    const int Wp = Wb + 2;
 
     std::vector<ImgDev> imgs(descs.size());
     long long n_rows = 0, tiles = 0, n_pix = 0, prev_end = 0;
@@ -150,20 +199,17 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     if (n_rows > 0 && (!params || !atlas_idx))
         return fail(c, DBMP_EINVAL, "params / atlas_idx is NULL");
     if (n_rows >= INT_MAX) return fail(c, DBMP_EINVAL, "too many primitives");
+    if ((long long)tiles * c->list_cap >= (1LL << 40))
+        return fail(c, DBMP_EINVAL, "tile lists too large");
 
-    int rc;
     const size_t ni = imgs.size();
     if ((rc = ensure(c, c->recs, sizeof(PrimRec) * (size_t)n_rows, st, "records"))) return rc;
-    if ((rc = ensure(c, c->tile_count, 4 * CNT_STRIDE * (size_t)tiles, st, "tile_count")))
-        return rc;
-    if ((rc = ensure(c, c->tile_start, 4 * (size_t)tiles, st, "tile_start"))) return rc;
-    if ((rc = ensure(c, c->pairs, 4 * (size_t)c->pair_cap, st, "pairs"))) return rc;
+    if ((rc = ensure_zeroed(c, c->tile_count, 4 * (size_t)tiles, st, "tile_count"))) return rc;
+    if ((rc = ensure(c, c->tile_len, 4 * (size_t)tiles, st, "tile_len"))) return rc;
+    if ((rc = ensure(c, c->loss_tile, 4 * (size_t)tiles, st, "loss_tile"))) return rc;
+    if ((rc = ensure(c, c->lists, 4 * (size_t)tiles * c->list_cap, st, "tile lists"))) return rc;
     if ((rc = ensure(c, c->saveK, 4 * (size_t)n_pix, st, "saveK"))) return rc;
     if ((rc = ensure(c, c->saveT, 4 * (size_t)n_pix, st, "saveT"))) return rc;
-    const size_t esz = dtype == DBMP_F32 ? 4 : 2;
-    if ((rc = ensure(c, c->atlas_pad, esz * (size_t)B * Hp * Wp, st, "atlas"))) return rc;
-    if ((rc = ensure(c, c->box, 16 * (size_t)B, st, "boxes"))) return rc;
-    if ((rc = ensure(c, c->flags, 4 * F_COUNT, st, "flags"))) return rc;
     if (c->imgs.cap < sizeof(ImgDev) * ni || !same_imgs(imgs, c->imgs_uploaded)) {
         if (capturing(st))
             return fail(c, DBMP_ESTATE,
@@ -180,20 +226,22 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     BinArgs ba{};
     ba.params = params; ba.idx = atlas_idx; ba.n_rows = n_rows;
     ba.imgs = (const ImgDev *)c->imgs.p; ba.n_images = (int)ni; ba.n_tiles = (int)tiles;
-    ba.atlas = atlas; ba.dtype = dtype; ba.B = B; ba.Hb = Hb; ba.Wb = Wb; ba.Wp = Wp;
+    ba.atlas = nullptr; ba.dtype = dtype; ba.B = B; ba.Hb = Hb; ba.Wb = Wb; ba.Wp = Wp;
     ba.alpha_max = alpha_max; ba.TS = tile; ba.atlas_pad = c->atlas_pad.p;
     ba.box = (int *)c->box.p; ba.recs = (PrimRec *)c->recs.p;
-    ba.tile_count = (int *)c->tile_count.p; ba.tile_start = (int *)c->tile_start.p;
-    ba.pairs = (int *)c->pairs.p; ba.pair_cap = c->pair_cap; ba.flags = (int *)c->flags.p;
+    ba.tile_count = (int *)c->tile_count.p; ba.lists = (int *)c->lists.p;
+    ba.list_cap = c->list_cap; ba.flags = (int *)c->flags.p; ba.pad_atlas = false;
     hipError_t e = launch_binning(ba, st);
     if (e != hipSuccess) return hip_fail(c, e, "binning launch");
 
     RasterArgs &ra = c->ra;
     ra = RasterArgs{};
     ra.recs = (const PrimRec *)c->recs.p;
-    ra.pairs = (const int *)c->pairs.p;
-    ra.tile_start = (const int *)c->tile_start.p;
-    ra.tile_count = (const int *)c->tile_count.p;
+    ra.lists = (const int *)c->lists.p;
+    ra.list_cap = c->list_cap;
+    ra.tile_count = (int *)c->tile_count.p;
+    ra.tile_len = (int *)c->tile_len.p;
+    ra.list_max = (int *)c->list_max.p;
     ra.imgs = (const ImgDev *)c->imgs.p;
     ra.n_images = (int)ni; ra.n_tiles = (int)tiles;
     ra.atlas_pad = c->atlas_pad.p; ra.dtype = dtype; ra.Wp = Wp; ra.Hb = Hb; ra.Wb = Wb;
@@ -201,9 +249,16 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.saveK = (int *)c->saveK.p; ra.saveT = (float *)c->saveT.p;
     ra.flags = (const int *)c->flags.p; ra.TS = tile;
     ra.pair_counter = (unsigned long long *)c->counter.p;
+    ra.loss_tile = (float *)c->loss_tile.p;
     e = launch_raster_fwd(ra, st);
-    if (e != hipSuccess) return hip_fail(c, e, "forward launch");
+    if (e != hipSuccess) {
+        // the appended counts were not consumed: clear them for the next forward
+        (void)hipStreamSynchronize(st);
+        (void)hipMemset(c->tile_count.p, 0, c->tile_count.cap);
+        return hip_fail(c, e, "forward launch");
+    }
     c->have_fwd = true;
+    c->have_loss = false;
     c->n_rows = n_rows;
     c->err.clear();
     return DBMP_OK;
@@ -213,27 +268,26 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
 
 extern "C" {
 
-int dbmp_create(dbmp_ctx **out, int device, long long pair_capacity)
+int dbmp_create(dbmp_ctx **out, int device, long long list_capacity)
 {
-    if (!out || pair_capacity < 0 || pair_capacity >= INT_MAX) return DBMP_EINVAL;
+    if (!out || list_capacity < 0 || list_capacity >= (1LL << 24)) return DBMP_EINVAL;
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DBMP_EINVAL;
     dbmp_ctx *c = new (std::nothrow) dbmp_ctx();
     if (!c) return DBMP_ENOMEM;
     c->device = device;
-    c->pair_cap = pair_capacity > 0 ? pair_capacity : (1LL << 20);
+    c->list_cap = list_capacity > 0 ? (int)list_capacity : 256;
     DeviceGuard g(device);
     int rc = ensure(c, c->flags, 4 * F_COUNT, nullptr, "flags");
-    if (rc) { delete c; return rc; }
-    (void)hipMemset(c->flags.p, 0, 4 * F_COUNT);
-    rc = ensure(c, c->counter, 8 * DBMP_COUNTER_SLOTS, nullptr, "counter");
-    if (rc) { delete c; return rc; }
-    (void)hipMemset(c->counter.p, 0, 8 * DBMP_COUNTER_SLOTS);
-    (void)hipDeviceSynchronize();
-    rc = ensure(c, c->pairs, 4 * (size_t)c->pair_cap, nullptr, "pairs");
-    if (rc) { delete c; return rc; }
-    c->pair_cap = (long long)(c->pairs.cap / 4);
+    if (!rc) rc = ensure(c, c->counter, 8 * DBMP_COUNTER_SLOTS, nullptr, "counter");
+    if (!rc) rc = ensure(c, c->list_max, 4 * DBMP_COUNTER_SLOTS, nullptr, "list_max");
+    if (rc) { dbmp_destroy(c); return rc; }
+    hipError_t e = hipMemset(c->flags.p, 0, 4 * F_COUNT);
+    if (e == hipSuccess) e = hipMemset(c->counter.p, 0, 8 * DBMP_COUNTER_SLOTS);
+    if (e == hipSuccess) e = hipMemset(c->list_max.p, 0, 4 * DBMP_COUNTER_SLOTS);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { dbmp_destroy(c); return DBMP_EHIP; }
     *out = c;
     return DBMP_OK;
 }
@@ -244,8 +298,9 @@ int dbmp_destroy(dbmp_ctx *c)
     {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        Buf *bs[] = {&c->recs, &c->tile_count, &c->tile_start, &c->pairs, &c->saveK,
-                     &c->saveT, &c->atlas_pad, &c->box, &c->imgs, &c->flags, &c->counter};
+        Buf *bs[] = {&c->recs, &c->tile_count, &c->tile_len, &c->lists, &c->saveK, &c->saveT,
+                     &c->atlas_pad, &c->box, &c->imgs, &c->flags, &c->counter, &c->list_max,
+                     &c->loss_tile};
         for (Buf *b : bs)
             if (b->p) (void)hipFree(b->p);
     }
@@ -253,21 +308,30 @@ int dbmp_destroy(dbmp_ctx *c)
     return DBMP_OK;
 }
 
-int dbmp_reserve(dbmp_ctx *c, long long pair_capacity)
+int dbmp_reserve(dbmp_ctx *c, long long list_capacity)
 {
-    if (!c || pair_capacity < 0 || pair_capacity >= INT_MAX) return DBMP_EINVAL;
-    if (pair_capacity <= c->pair_cap) return DBMP_OK;
+    if (!c || list_capacity < 0 || list_capacity >= (1LL << 24)) return DBMP_EINVAL;
     DeviceGuard g(c->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
-    int rc = ensure(c, c->pairs, 4 * (size_t)pair_capacity, nullptr, "pairs");
-    if (rc) return rc;
-    c->pair_cap = std::min<long long>((long long)(c->pairs.cap / 4), INT_MAX - 1);
-    e = hipMemset((int *)c->flags.p + F_S_TOTALMAX, 0, sizeof(int));
+    if (list_capacity > c->list_cap) {
+        c->list_cap = (int)list_capacity;  // the list buffer grows at the next forward
+        c->have_fwd = false;               // the lists of the last forward are stale
+    }
+    e = hipMemset(c->list_max.p, 0, 4 * DBMP_COUNTER_SLOTS);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(c, e, "flag reset");
-    c->have_fwd = false;  // the lists of the last forward are gone
+    if (e != hipSuccess) return hip_fail(c, e, "statistics reset");
     return DBMP_OK;
+}
+
+int dbmp_set_atlas(dbmp_ctx *c, dbmp_stream stream, const void *atlas, int B, int Hb, int Wb,
+                   int atlas_dtype)
+{
+    if (!c) return DBMP_EINVAL;
+    DeviceGuard g(c->device);
+    int rc = set_atlas_impl(c, (hipStream_t)stream, atlas, B, Hb, Wb, atlas_dtype);
+    if (!rc) c->err.clear();
+    return rc;
 }
 
 int dbmp_render(dbmp_ctx *c, dbmp_stream stream, const float *params, const int32_t *atlas_idx,
@@ -318,6 +382,38 @@ int dbmp_render_backward(dbmp_ctx *c, dbmp_stream stream, const float *dL_dimage
     return DBMP_OK;
 }
 
+int dbmp_render_backward_mse(dbmp_ctx *c, dbmp_stream stream, const float *target,
+                             const float *dL_dalpha, float *dL_dparams, int accumulate)
+{
+    if (!c) return DBMP_EINVAL;
+    if (!c->have_fwd) return fail(c, DBMP_ESTATE, "no forward on this context");
+    if (!target || (c->n_rows > 0 && !dL_dparams))
+        return fail(c, DBMP_EINVAL, "target / dL_dparams is NULL");
+    DeviceGuard g(c->device);
+    RasterArgs a = c->ra;
+    a.target = target;
+    a.gA = dL_dalpha;
+    a.dparams = dL_dparams;
+    a.n_param_floats = accumulate ? 0 : c->n_rows * 8;  // 0: no clear before accumulating
+    hipError_t e = launch_raster_bwd(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "backward launch");
+    c->have_loss = true;
+    c->err.clear();
+    return DBMP_OK;
+}
+
+int dbmp_mse_loss(dbmp_ctx *c, dbmp_stream stream, float *out)
+{
+    if (!c) return DBMP_EINVAL;
+    if (!c->have_loss) return fail(c, DBMP_ESTATE, "no dbmp_render_backward_mse on this context");
+    if (!out) return fail(c, DBMP_EINVAL, "out is NULL");
+    DeviceGuard g(c->device);
+    hipError_t e = launch_loss_sum(c->ra.loss_tile, c->ra.imgs, c->ra.n_images, out,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "loss launch");
+    return DBMP_OK;
+}
+
 int dbmp_check(dbmp_ctx *c, dbmp_stream stream)
 {
     if (!c) return DBMP_EINVAL;
@@ -333,23 +429,24 @@ int dbmp_check(dbmp_ctx *c, dbmp_stream stream)
         if (e != hipSuccess) return hip_fail(c, e, "flag reset");
     }
     if (f[F_S_OVERFLOW])
-        return fail(c, DBMP_EOVERFLOW, "pair buffer too small: " +
-                                           std::to_string(f[F_S_TOTALMAX]) +
-                                           " pairs needed, capacity " +
-                                           std::to_string(c->pair_cap));
+        return fail(c, DBMP_EOVERFLOW, "a tile list exceeds the capacity of " +
+                                           std::to_string(c->list_cap) +
+                                           " entries; see dbmp_longest_list");
     if (f[F_S_BADIDX]) return fail(c, DBMP_EINVAL, "atlas index out of range");
     if (f[F_S_NONFINITE]) return fail(c, DBMP_ENONFINITE, "non-finite parameter or texel");
     return DBMP_OK;
 }
 
-long long dbmp_pair_count(dbmp_ctx *c, dbmp_stream stream)
+long long dbmp_longest_list(dbmp_ctx *c, dbmp_stream stream)
 {
     if (!c) return -1;
     DeviceGuard g(c->device);
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return -1;
-    int f[F_COUNT];
-    if (hipMemcpy(f, c->flags.p, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess) return -1;
-    return f[F_S_TOTALMAX];
+    std::vector<int> m(DBMP_COUNTER_SLOTS);
+    if (hipMemcpy(m.data(), c->list_max.p, 4 * DBMP_COUNTER_SLOTS, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return -1;
+    return *std::max_element(m.begin(), m.end());
 }
 
 long long dbmp_support_pairs(dbmp_ctx *c, dbmp_stream stream, int reset)

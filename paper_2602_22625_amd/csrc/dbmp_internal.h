@@ -8,16 +8,11 @@ namespace dbmp {
 
 // Device-side flag slots (int32 each) kept in the context workspace.
 enum Flag : int {
-    // per forward (reset at the start of every forward)
-    F_OVERFLOW = 0,     // more (tile, primitive) pairs than the pair buffer holds
-    F_BADIDX = 1,       // an atlas index outside [0, B)
-    F_NONFINITE = 2,    // a non-finite parameter / texel / scale
-    F_TOTAL = 3,        // number of (tile, primitive) pairs of this forward (clamped to INT_MAX)
-    // sticky (raised by any forward; errors cleared by dbmp_check, the maximum by dbmp_reserve)
-    F_S_OVERFLOW = 4,
-    F_S_BADIDX = 5,
-    F_S_NONFINITE = 6,
-    F_S_TOTALMAX = 7,   // largest per-forward pair count since the last reserve
+    // Raised by any forward; cleared (and reported) by dbmp_check. A tile whose list did not
+    // fit also knows it locally (its count exceeds the capacity) and renders nothing.
+    F_S_OVERFLOW = 0,   // a tile's list is longer than the list capacity
+    F_S_BADIDX = 1,     // an atlas index outside [0, B)
+    F_S_NONFINITE = 2,  // a non-finite parameter / texel / scale
     F_COUNT = 16
 };
 
@@ -25,11 +20,8 @@ enum Flag : int {
 // (2^-64) get a zero gradient; their exact gradient is below TAU times an O(1) factor.
 #define DBMP_TAU 5.42101086242752217e-20f
 
-// Per-tile pair counters are updated by device-scope atomics, which serialise per cache line;
-// each counter therefore gets a 128-byte line of its own (tile t at tile_count[t * CNT_STRIDE]).
-#define CNT_STRIDE 32
-
-// The evaluated-pair counter is spread over this many 64-bit slots (summed when read).
+// The evaluated-pair counter and the longest-list statistic are spread over this many slots
+// (summed / max-reduced when read) so that no single address is hot.
 #define DBMP_COUNTER_SLOTS 1024
 
 // One image of a (possibly batched) launch.
@@ -43,8 +35,8 @@ struct ImgDev {
 };
 
 // Per-primitive record written by the setup kernel and read (wave-uniformly, through the scalar
-// cache) by the raster kernels. Coordinates are those of the padded bitmap, where the texel
-// (r, c) of Eq. (2) sits at padded (r + 1, c + 1):
+// cache) by the raster kernels; the fields the forward needs come first. Coordinates are those
+// of the padded bitmap, where the texel (r, c) of Eq. (2) sits at padded (r + 1, c + 1):
 //     U' = aU x + bU y + eU = U + 1,   V' = aV x + bV y + eV = V + 1.
 struct __attribute__((aligned(16))) PrimRec {
     double aU, bU, eU;
@@ -53,13 +45,14 @@ struct __attribute__((aligned(16))) PrimRec {
     float ka;                   // alpha_max * sigmoid(nu)
     float cr, cg, cb;           // sigmoid of the colour logits
     int tex;                    // element offset of the padded bitmap's (0, 0)
-    float omsig;                // 1 - sigmoid(nu)
+    float kaom;                 // alpha_max * sigmoid(nu) * (1 - sigmoid(nu))  (d alpha / d nu / M)
+    float ccr, ccg, ccb;        // c (1 - c): derivative of the colour sigmoid
     float faU, fbU, faV, fbV;   // float copies of the map's linear part (backward chain rule)
     int tx0, tx1, ty0, ty1;     // tile span of the support's bounding box (empty: tx0 > tx1)
-    int img;
-    int pad[3];
+    int img, tile_off, ntx, W, H;  // the primitive's image: first tile, tiles per row, size
+    int pad[2];
 };
-static_assert(sizeof(PrimRec) == 160, "PrimRec layout");
+static_assert(sizeof(PrimRec) == 176, "PrimRec layout");
 
 __device__ __forceinline__ int find_by_prim(const ImgDev *__restrict__ imgs, int n, long long g)
 {
@@ -114,15 +107,20 @@ struct BinArgs {
     void *atlas_pad;
     int *box;
     PrimRec *recs;
-    int *tile_count, *tile_start;
-    int *pairs;
-    long long pair_cap;
+    int *tile_count;   // entries per tile list (zero on entry; the forward raster re-zeroes)
+    int *lists;        // tile t's list at lists[t * list_cap]
+    int list_cap;
     int *flags;
+    bool pad_atlas;    // pad the atlas and find its boxes (false: reuse the stored ones)
 };
 
 struct RasterArgs {
     const PrimRec *recs;
-    const int *pairs, *tile_start, *tile_count;
+    const int *lists;
+    int *tile_count;   // the forward reads each tile's count, stores it in tile_len, zeroes it
+    int *tile_len;
+    int list_cap;
+    int *list_max;     // per-slot longest list seen since the last reserve
     const ImgDev *imgs;
     int n_images, n_tiles;
     const void *atlas_pad;
@@ -138,10 +136,14 @@ struct RasterArgs {
     const int *flags;
     int TS;
     unsigned long long *pair_counter;  // cumulative count of evaluated (pixel, primitive) pairs
+    const float *target;               // non-NULL: the backward forms the MSE gradient itself
+    float *loss_tile;                  // per-tile sums of squared errors (MSE backward)
 };
 
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);
+hipError_t launch_loss_sum(const float *loss_tile, const ImgDev *imgs, int n_images, float *out,
+                           hipStream_t st);
 
 }  // namespace dbmp

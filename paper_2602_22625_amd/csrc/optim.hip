@@ -62,9 +62,9 @@ k_mse_grad(const float4 *__restrict__ img, const float4 *__restrict__ tgt, long 
 }
 
 __global__ void __launch_bounds__(256)
-k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+k_adam(float *__restrict__ p, float *__restrict__ g, float *__restrict__ m,
        float *__restrict__ v, long long n, float lr, float b1, float b2, float eps,
-       int *__restrict__ step, unsigned int *__restrict__ done)
+       int *__restrict__ step, unsigned int *__restrict__ done, int zero_grad)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int t = *step + 1;
@@ -73,6 +73,7 @@ k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m
         const float c1 = (float)(1.0 - pow((double)b1, (double)t));
         const float c2 = (float)(1.0 - pow((double)b2, (double)t));
         const float gi = g[i];
+        if (zero_grad) g[i] = 0.f;  // ready for the next accumulating backward
         const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
         const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
         m[i] = mi;
@@ -113,15 +114,16 @@ extern "C" int dbmp_mse_grad(dbmp_stream stream, const float *image, const float
     return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP;
 }
 
-extern "C" int dbmp_adam_step(dbmp_stream stream, float *params, const float *grad, float *m,
+extern "C" int dbmp_adam_step(dbmp_stream stream, float *params, float *grad, float *m,
                               float *v, long long n, float lr, float beta1, float beta2,
-                              float eps, int32_t *step)
+                              float eps, int32_t *step, int zero_grad)
 {
     if (n < 0 || !step || (n > 0 && (!params || !grad || !m || !v))) return DBMP_EINVAL;
     if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
         return DBMP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     k_adam<<<(unsigned)(n > 0 ? (n + 255) / 256 : 1), 256, 0, st>>>(
-        params, grad, m, v, n, lr, beta1, beta2, eps, step, (unsigned int *)(step + 1));
+        params, grad, m, v, n, lr, beta1, beta2, eps, step, (unsigned int *)(step + 1),
+        zero_grad);
     return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP;
 }

@@ -9,11 +9,13 @@
 //
 // Precision: the canvas -> bitmap map is evaluated in float64 (2 FMAs per coordinate; on
 // gfx950 a float64 FMA issues at the rate of a non-packed float32 one), so the bilinear weights
-// carry float32 precision even at U ~ 128; sampling and compositing are float32.
+// carry float32 precision even at U ~ 128; sampling and compositing are float32. Inside the
+// support U', V' >= 0, so the texel index is the truncation and the weight the fraction.
 //
-// Forward: front to back, C += T alpha c, T *= (1 - alpha) (Eqs. 4-5), I = C + T b, A = 1 - T.
-// It stores no per-layer state; per pixel it keeps the list position K of the last layer in
-// front of which T >= TAU, and T_K.
+// Forward: the workgroup first sorts its tile's list ascending (front to back) in LDS and
+// writes it back for the backward, then composites C += T alpha c, T *= (1 - alpha) (Eqs. 4-5),
+// I = C + T b, A = 1 - T. It stores no per-layer state; per pixel it keeps the list position K
+// of the last layer in front of which T >= TAU, and T_K.
 //
 // Backward: the list is walked back to front. Transmittance is recovered per layer from the
 // pixel's saved (K, T_K): T_j = T_{j+1} / (1 - alpha_j) for j < K (the same float32 factor the
@@ -25,10 +27,13 @@
 //     dL/dnu_j    = dL/dalpha_j alpha_max sigma (1 - sigma) M
 //     dL/dU', dL/dV' = dL/dalpha_j alpha_max sigma (dM/dU, dM/dV), then through Eq. (1)-(2) to
 //     x, y, log s, theta (Eq. 7).
-// The 8 per-lane partials are reduced across the wave with a transposed butterfly (after three
-// exchange steps each lane carries one of the 8 sums) and added to dL/dparams with one
-// float32 atomic per (wave, primitive, parameter).
+// The 8 per-lane partials are reduced across the wave by a transposed butterfly built from
+// gfx950's cross-row lane swaps (v_permlane32_swap, v_permlane16_swap) and DPP row/quad
+// permutes, after which lane 8q holds the wave total of parameter q; eight lanes then issue
+// one float32 atomic each per (wave, primitive).
 #include "dbmp_internal.h"
+
+#include <limits.h>
 
 namespace dbmp {
 
@@ -58,15 +63,24 @@ __device__ __forceinline__ TileGeom<TS> tile_geom(int tile, const ImgDev *__rest
     return tg;
 }
 
-// Bilinear sample of the padded bitmap at (U', V') (Supp. Eqs. S1-S3). Returns M and its
-// derivatives along U' and V' on the floor cell.
+// Lanes of the wave whose pixel lies in the primitive's support: four float64 compares whose
+// lane masks are combined on the scalar unit.
+__device__ __forceinline__ uint64_t support_mask(const PrimRec &r, double U, double V,
+                                                 uint64_t valid)
+{
+    return __ballot(U >= r.Ulo) & __ballot(U < r.Uhi) & __ballot(V >= r.Vlo) &
+           __ballot(V < r.Vhi) & valid;
+}
+
+// Bilinear sample of the padded bitmap at (U', V') >= 0 (Supp. Eqs. S1-S3): M and its
+// derivatives along U' and V' on the floor cell. Forward and backward call this same code, so
+// both obtain bit-identical alpha (the backward's transmittance recovery relies on it).
 template <typename TexT>
 __device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex, int Wp, double U,
                                          double V, float &M, float &MU, float &MV)
 {
-    const double fU = floor(U), fV = floor(V);
-    const float wu = (float)(U - fU), wv = (float)(V - fV);
-    const int iu = (int)fU, iv = (int)fV;
+    const float wu = (float)__builtin_amdgcn_fract(U), wv = (float)__builtin_amdgcn_fract(V);
+    const int iu = (int)U, iv = (int)V;
     const TexT *t = atlas + (tex + iv * Wp + iu);
     const float p00 = texel<TexT>(t[0]), p01 = texel<TexT>(t[1]);
     const float p10 = texel<TexT>(t[Wp]), p11 = texel<TexT>(t[Wp + 1]);
@@ -78,56 +92,118 @@ __device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex
     MU = fmaf(wv, d1 - d0, d0);
 }
 
-// Lanes of the wave whose pixel lies in the primitive's support: four float64 compares whose
-// lane masks are combined on the scalar unit.
-__device__ __forceinline__ uint64_t support_mask(const PrimRec &r, double U, double V,
-                                                 uint64_t valid)
+template <int TS>
+struct SortCap {
+    static constexpr int v = TS == 8 ? 512 : (TS == 16 ? 2048 : 4096);
+};
+
+// Ascending bitonic network with only ascending comparators (the first sub-stage of every merge
+// compares i with i ^ (k - 1)): a list of any length n behaves as if padded with +inf, and
+// comparators reaching past n are skipped. Executed by all NT threads of the workgroup.
+template <int NT, typename Get, typename Set, typename Sync>
+__device__ __forceinline__ void bitonic_sort(int n, Get get, Set set, Sync sync)
 {
-    return __ballot(U >= r.Ulo) & __ballot(U < r.Uhi) & __ballot(V >= r.Vlo) &
-           __ballot(V < r.Vhi) & valid;
+    int N2 = 1;
+    while (N2 < n) N2 <<= 1;
+    for (int k = 2; k <= N2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < N2; i += NT) {
+                const int l = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+                if (l > i && l < n) {
+                    const int x = get(i), y = get(l);
+                    if (y < x) { set(i, y); set(l, x); }
+                }
+            }
+            sync();
+        }
+    }
 }
 
 template <int TS, typename TexT, bool BG_PP>
 __global__ void __launch_bounds__(TS * TS)
-k_raster_fwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
-             const int *__restrict__ tile_start, const int *__restrict__ tile_count,
+k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
+             int *__restrict__ tile_count, int *__restrict__ tile_len, int *__restrict__ list_max,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
              const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
              float *__restrict__ saveT, const int *__restrict__ flags,
              unsigned long long *__restrict__ pair_counter)
 {
-    if (flags[F_OVERFLOW]) return;
+    constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
+    __shared__ __attribute__((aligned(16))) int s_ids[CAP + 4];
     const int tile = xcd_remap(blockIdx.x, n_tiles);
+    const int n = tile_count[tile];
+    __syncthreads();  // every lane has read the count before it is re-armed
+    if (threadIdx.x == 0) {
+        tile_count[tile] = 0;  // ready for the next forward's appends
+        tile_len[tile] = n;    // for the backward
+        atomicMax(list_max + (blockIdx.x & (DBMP_COUNTER_SLOTS - 1)), n);  // statistic
+    }
+    if (n > list_cap) return;  // this tile's list did not fit (reported by dbmp_check)
     const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
+    int *seg = lists + (size_t)tile * list_cap;
+    const bool in_lds = n <= CAP;
+
+    // ---- sort the tile's list front to back (index order) and write it back -----------------
+    if (in_lds) {
+        for (int i = threadIdx.x; i < n + 4; i += NT) s_ids[i] = i < n ? seg[i] : INT_MAX;
+        __syncthreads();
+        if (n <= NT) {  // rank sort: entries are distinct primitive ids
+            int v = INT_MAX, rank = 0;
+            if ((int)threadIdx.x < n) {
+                v = s_ids[threadIdx.x];
+                for (int k = 0; k < n; k += 4) {
+                    const int4 q = *reinterpret_cast<const int4 *>(&s_ids[k]);
+                    rank += (q.x < v) + (q.y < v) + (q.z < v) + (q.w < v);
+                }
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < n) s_ids[rank] = v;
+        } else {
+            bitonic_sort<NT>(n, [&](int i) { return s_ids[i]; },
+                             [&](int i, int x) { s_ids[i] = x; }, [] { __syncthreads(); });
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) seg[i] = s_ids[i];
+    } else {  // longer than the LDS buffer: sort in place in global memory
+        volatile int *vs = seg;
+        bitonic_sort<NT>(n, [&](int i) { return vs[i]; }, [&](int i, int x) { vs[i] = x; },
+                         [] { __threadfence_block(); __syncthreads(); });
+    }
+
+    // ---- composite ------------------------------------------------------------------------
     const double xd = tg.px, yd = tg.py;
     const uint64_t vmask = __ballot(tg.valid);
-    const int start = tile_start[tile], n = tile_count[(size_t)tile * CNT_STRIDE];
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, TK = 1.f;
     int K = -1;
     unsigned long long npairs = 0;  // wave-uniform count of evaluated (pixel, primitive) pairs
-    for (int j = 0; j < n; ++j) {
-        const PrimRec &r = recs[pairs[start + j]];
-        const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-        const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-        const uint64_t m = support_mask(r, U, V, vmask);
-        if (m == 0) continue;  // no lane of this wave touches the primitive
-        npairs += __popcll(m);
-        const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
-        if (in) {
-            float M, MU, MV;
-            bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
-            const float a = r.ka * M;  // Eq. (3)
-            if (T >= DBMP_TAU) { K = j; TK = T; }
-            const float w = T * a;
-            C0 = fmaf(w, r.cr, C0);
-            C1 = fmaf(w, r.cg, C1);
-            C2 = fmaf(w, r.cb, C2);
-            T = T * (1.f - a);
+    auto composite = [&](auto id_at) {
+        for (int j = 0; j < n; ++j) {
+            const PrimRec &r = recs[id_at(j)];
+            const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+            const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+            const uint64_t m = support_mask(r, U, V, vmask);
+            if (m == 0) continue;  // no lane of this wave touches the primitive
+            npairs += __popcll(m);
+            if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+                float M, MU, MV;
+                bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
+                const float a = r.ka * M;  // Eq. (3)
+                if (T >= DBMP_TAU) { K = j; TK = T; }
+                const float w = T * a;
+                C0 = fmaf(w, r.cr, C0);
+                C1 = fmaf(w, r.cg, C1);
+                C2 = fmaf(w, r.cb, C2);
+                T = T * (1.f - a);
+            }
         }
-    }
+    };
+    if (in_lds)
+        composite([&](int j) { return __builtin_amdgcn_readfirstlane(s_ids[j]); });
+    else
+        composite([&](int j) { return __builtin_amdgcn_readfirstlane(((volatile int *)seg)[j]); });
     if ((threadIdx.x & 63) == 0 && npairs)  // spread over slots: no single hot address
-        atomicAdd(pair_counter + ((blockIdx.x * (TS * TS / 64) + (threadIdx.x >> 6)) &
+        atomicAdd(pair_counter + ((blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) &
                                   (DBMP_COUNTER_SLOTS - 1)),
                   npairs);
     if (!tg.valid) return;
@@ -150,46 +226,77 @@ k_raster_fwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
     saveT[gp] = TK;
 }
 
-// Wave-wide sum of 8 values per lane. Three exchange steps (lane bits 5, 4, 3) halve the
-// number of live values each time; three more add within groups of 8 lanes. On return lane l
-// holds the wave total of value (l >> 3).
+// ------------------------------------------------------------------------------------------
+// Wave reduction of 8 values per lane.
+// ------------------------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Transposed butterfly: v_permlane32_swap leaves values 0-3 summed over lanes l and l^32 in the
+// low half and values 4-7 in the high half; v_permlane16_swap halves again across rows; a
+// row_mirror step (with a select) across the two 8-lane halves of a row; then row_half_mirror,
+// quad_perm [1,0,3,2] and [2,3,0,1] add within groups of 8. On return lane l holds the wave
+// total of value (l >> 3). 18 VALU instructions, no LDS.
 __device__ __forceinline__ float reduce8(const float (&v)[8], int lane)
 {
-    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
     float w[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const float send = h5 ? v[i] : v[i + 4];
-        const float keep = h5 ? v[i + 4] : v[i];
-        w[i] = keep + __shfl_xor(send, 32);
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                        __float_as_uint(v[i + 4]), false, false);
+        w[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
     float x[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const float send = h4 ? w[i] : w[i + 2];
-        const float keep = h4 ? w[i + 2] : w[i];
-        x[i] = keep + __shfl_xor(send, 16);
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[i]),
+                                                        __float_as_uint(w[i + 2]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    float y = (h3 ? x[1] : x[0]) + __shfl_xor(h3 ? x[0] : x[1], 8);
-    y += __shfl_xor(y, 4);
-    y += __shfl_xor(y, 2);
-    y += __shfl_xor(y, 1);
+    const bool h3 = lane & 8;
+    float y = (h3 ? x[1] : x[0]) + dpp<0x140>(h3 ? x[0] : x[1]);  // row_mirror
+    y += dpp<0x141>(y);                                            // row_half_mirror
+    y += dpp<0xB1>(y);                                             // quad_perm [1,0,3,2]
+    y += dpp<0x4E>(y);                                             // quad_perm [2,3,0,1]
     return y;
 }
 
-template <int TS, typename TexT, bool BG_PP, bool HAS_GA>
+// Sum of one value over the wave (result valid in every lane).
+__device__ __forceinline__ float wave_sum(float y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false,
+                                                    false);
+    y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false,
+                                                    false);
+    y = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    y += dpp<0x140>(y);
+    y += dpp<0x141>(y);
+    y += dpp<0xB1>(y);
+    y += dpp<0x4E>(y);
+    return y;
+}
+
+// MSE: the backward forms dL/dI = scale (I - target) itself from the forward's image and writes
+// the workgroup's sum of squared differences to loss_tile[tile] (reduced on request).
+template <int TS, typename TexT, bool BG_PP, bool HAS_GA, bool MSE>
 __global__ void __launch_bounds__(TS * TS)
-k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
-             const int *__restrict__ tile_start, const int *__restrict__ tile_count,
+k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, int list_cap,
+             const int *__restrict__ tile_len,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
              const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
              const int *__restrict__ saveK, const float *__restrict__ saveT,
-             const float *__restrict__ gI, const float *__restrict__ gA,
+             const float *__restrict__ gI, const float *__restrict__ target,
+             float *__restrict__ loss_tile, const float *__restrict__ gA,
              float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
              const int *__restrict__ flags)
 {
-    if (flags[F_OVERFLOW]) return;
     const int tile = xcd_remap(blockIdx.x, n_tiles);
+    const int n = tile_len[tile];
+    if (n > list_cap) return;  // the forward did not render this tile
     const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
     const int lane = threadIdx.x & 63;
     const ImgDev &D = tg.D;
@@ -198,10 +305,18 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
     const size_t plane = (size_t)D.H * D.W;
     const long long gp = D.pix_off + tg.pix;
     float g0 = 0.f, g1 = 0.f, g2 = 0.f, ga = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, TK = 0.f;
+    float sq = 0.f;
     int K = -1;
     if (tg.valid) {
-        const float *gp3 = gI + 3 * D.pix_off + tg.pix;
+        const float *gp3 = gI + 3 * D.pix_off + tg.pix;  // MSE: the forward's image
         g0 = gp3[0]; g1 = gp3[plane]; g2 = gp3[2 * plane];
+        if (MSE) {
+            const float *tp = target + 3 * D.pix_off + tg.pix;
+            const float e0 = g0 - tp[0], e1 = g1 - tp[plane], e2 = g2 - tp[2 * plane];
+            sq = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+            const float sc = 2.f / (3.f * (float)plane);  // mean over the image's 3HW values
+            g0 = sc * e0; g1 = sc * e1; g2 = sc * e2;
+        }
         if (HAS_GA) ga = gA[gp];
         if (BG_PP) {
             const float *bp = bg + 3 * D.pix_off + tg.pix;
@@ -213,29 +328,28 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
         TK = saveT[gp];
     }
     float Bk = 1.f, Trun = TK;
-    const int start = tile_start[tile], n = tile_count[(size_t)tile * CNT_STRIDE];
+    const int *seg = lists + (size_t)tile * list_cap;
+    int gnext = n > 0 ? seg[n - 1] : 0;
     for (int j = n - 1; j >= 0; --j) {
-        const int g = pairs[start + j];
+        const int g = gnext;
+        if (j > 0) gnext = seg[j - 1];  // next id, loaded while this one is processed
         const PrimRec &r = recs[g];
         const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
         const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-        const uint64_t m = support_mask(r, U, V, vmask);
-        if (m == 0) continue;  // no lane of this wave touches the primitive
-        const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
+        const uint64_t msk = support_mask(r, U, V, vmask);
+        if (msk == 0) continue;
         float d[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) d[q] = 0.f;
-        if (in) {
+        if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
             float M, MU, MV;
             bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
             const float a = r.ka * M;
             const float m = 1.f - a;
-            float Tj = 0.f;
-            if (j == K) {
-                Tj = TK;
-            } else if (j < K) {
-                Tj = Trun / m;
-            }
+            // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
+            float rc = __builtin_amdgcn_rcpf(m);
+            rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
+            const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
             Trun = Tj;
             const float cr = r.cr, cg = r.cg, cb = r.cb;
             float dal = g0 * (cr - G0);
@@ -244,17 +358,17 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
             if (HAS_GA) dal = fmaf(ga, Bk, dal);
             dal *= Tj;
             const float ta = Tj * a;
-            d[5] = g0 * ta * cr * (1.f - cr);
-            d[6] = g1 * ta * cg * (1.f - cg);
-            d[7] = g2 * ta * cb * (1.f - cb);
+            d[5] = g0 * ta * r.ccr;
+            d[6] = g1 * ta * r.ccg;
+            d[7] = g2 * ta * r.ccb;
+            d[4] = dal * r.kaom * M;
             const float dM = dal * r.ka;
-            d[4] = dM * r.omsig * M;
             const float gU = dM * MU, gV = dM * MV;
             const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
-            d[0] = -(gU * r.faU + gV * r.faV);
-            d[1] = -(gU * r.fbU + gV * r.fbV);
-            d[2] = -(gU * Ub + gV * Vb);
-            d[3] = gU * cu_cv * Vb - gV * cv_cu * Ub;
+            d[0] = -fmaf(gU, r.faU, gV * r.faV);
+            d[1] = -fmaf(gU, r.fbU, gV * r.fbV);
+            d[2] = -fmaf(gU, Ub, gV * Vb);
+            d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
             G0 = fmaf(m, G0, a * cr);
             G1 = fmaf(m, G1, a * cg);
             G2 = fmaf(m, G2, a * cb);
@@ -262,6 +376,17 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ pairs,
         }
         const float tot = reduce8(d, lane);
         if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)g * 8 + (lane >> 3), tot);
+    }
+    if (MSE) {
+        __shared__ float s_loss[TS * TS / 64];
+        const float ws = wave_sum(sq);
+        if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int w = 0; w < TS * TS / 64; ++w) t += s_loss[w];
+            loss_tile[tile] = t;
+        }
     }
 }
 
@@ -271,27 +396,47 @@ __global__ void k_fill0(float *__restrict__ p, long long n)
     if (i < n) p[i] = 0.f;
 }
 
+// Per-image sums of the per-tile squared errors: one workgroup per image, out[image].
+__global__ void __launch_bounds__(256) k_loss_sum(const float *__restrict__ lt,
+                                                  const ImgDev *__restrict__ imgs,
+                                                  float *__restrict__ out)
+{
+    const ImgDev D = imgs[blockIdx.x];
+    const int nt = D.ntx * D.nty;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nt; i += 256) acc += lt[D.tile_off + i];
+    __shared__ double s[256];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = (float)s[0];
+}
+
 // ------------------------------------------------------------------------------------------
 // Host launchers
 // ------------------------------------------------------------------------------------------
-
 template <int TS, typename TexT, bool BGPP>
 static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
     k_raster_fwd<TS, TexT, BGPP><<<a.n_tiles, TS * TS, 0, st>>>(
-        a.recs, a.pairs, a.tile_start, a.tile_count, a.imgs, a.n_images, a.n_tiles,
-        (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK, a.saveT, a.flags,
-        a.pair_counter);
+        a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len, a.list_max,
+        a.imgs,
+        a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
+        a.saveT, a.flags, a.pair_counter);
 }
 
-template <int TS, typename TexT, bool BGPP, bool GA>
+template <int TS, typename TexT, bool BGPP, bool GA, bool MSE>
 static void bwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
-    k_raster_bwd<TS, TexT, BGPP, GA><<<a.n_tiles, TS * TS, 0, st>>>(
-        a.recs, a.pairs, a.tile_start, a.tile_count, a.imgs, a.n_images, a.n_tiles,
-        (const TexT *)a.atlas_pad, a.Wp, a.bg, a.saveK, a.saveT, a.gI, a.gA, a.dparams, cu + 1.0,
-        cv + 1.0, (float)(cu / cv), (float)(cv / cu), a.flags);
+    k_raster_bwd<TS, TexT, BGPP, GA, MSE><<<a.n_tiles, TS * TS, 0, st>>>(
+        a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
+        (const TexT *)a.atlas_pad, a.Wp, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI, a.target,
+        a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
+        (float)(cv / cu), a.flags);
 }
 
 template <int TS, typename TexT>
@@ -305,10 +450,16 @@ static void fwd_d0(const RasterArgs &a, hipStream_t st)
     if (a.dtype == 0) fwd_d1<TS, float>(a, st); else fwd_d1<TS, uint16_t>(a, st);
 }
 
+template <int TS, typename TexT, bool BGPP, bool GA>
+static void bwd_d3(const RasterArgs &a, hipStream_t st)
+{
+    if (a.target) bwd_t<TS, TexT, BGPP, GA, true>(a, st);
+    else bwd_t<TS, TexT, BGPP, GA, false>(a, st);
+}
 template <int TS, typename TexT, bool BGPP>
 static void bwd_d2(const RasterArgs &a, hipStream_t st)
 {
-    if (a.gA) bwd_t<TS, TexT, BGPP, true>(a, st); else bwd_t<TS, TexT, BGPP, false>(a, st);
+    if (a.gA) bwd_d3<TS, TexT, BGPP, true>(a, st); else bwd_d3<TS, TexT, BGPP, false>(a, st);
 }
 template <int TS, typename TexT>
 static void bwd_d1(const RasterArgs &a, hipStream_t st)
@@ -345,6 +496,13 @@ hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st)
         default: bwd_d0<32>(a, st); break;
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_sum(const float *loss_tile, const ImgDev *imgs, int n_images, float *out,
+                           hipStream_t st)
+{
+    k_loss_sum<<<n_images, 256, 0, st>>>(loss_tile, imgs, out);
     return hipGetLastError();
 }
 

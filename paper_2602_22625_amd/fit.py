@@ -2,10 +2,10 @@
 optionally captured once into a HIP graph and replayed per step (Supp. Table S1 loss/optimiser,
 flat learning rate).
 
-The pair buffer is sized from the first (checked) step with headroom; replays are asynchronous,
-and `check()` polls the device flags (overflow, invalid input) every `check_every` steps. On
-overflow the buffer is grown, the graph is captured again and the steps since the last good
-check are repeated from a saved copy of the state.
+The per-tile list capacity is sized from the first (checked) step with headroom; replays are
+asynchronous, and `run()` polls the device flags (overflow, invalid input) every `check_every`
+steps. On overflow the capacity is raised, the graph is captured again and the steps since the
+last good poll are repeated from a saved copy of the state.
 """
 from __future__ import annotations
 
@@ -17,7 +17,8 @@ from .render import Renderer
 
 class Fitter:
     def __init__(self, params, atlas_idx, atlas, target, bg=None, alpha_max=1.0, tile=16,
-                 lr=1e-2, betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0):
+                 lr=1e-2, betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0,
+                 accumulate=True):
         dev = params.device
         self.H, self.W = int(target.shape[1]), int(target.shape[2])
         self.params = params.detach().clone().contiguous()
@@ -33,31 +34,33 @@ class Fitter:
         self.step_count = torch.zeros(2, dtype=torch.int32, device=dev)  # [steps, scratch]
         self.grad = torch.zeros_like(self.params)
         self.image = torch.empty(3, self.H, self.W, device=dev, dtype=torch.float32)
-        self.gimage = torch.empty_like(self.image)
-        self.loss_buf = torch.zeros(3, device=dev, dtype=torch.float32)  # [sum sq, scratch x2]
+        self.loss_buf = torch.zeros(1, device=dev, dtype=torch.float32)
         self.R = renderer if renderer is not None else Renderer(device=dev.index, check=False)
         self.headroom = headroom
+        self.accumulate = accumulate  # backward adds into grad, Adam zeroes it (no clear kernel)
         self.graph = None
         self._sized = False
 
-    # one Adam iteration, enqueued on the current stream
+    # One Adam iteration, enqueued on the current stream: forward (the atlas was stored once),
+    # backward with the MSE gradient formed inside the kernel and accumulated into a gradient
+    # buffer that Adam zeroes after reading: four kernels per step.
     def _enqueue(self):
         st = capi.stream_handle()
-        self.R.render(self.params, self.atlas_idx, self.atlas, self.H, self.W, self.bg,
+        self.R.render(self.params, self.atlas_idx, None, self.H, self.W, self.bg,
                       self.alpha_max, self.tile, image=self.image, with_alpha=False)
-        capi.dbmp_mse_grad(st, self.image, self.target, self.image.numel(), self.gimage,
-                           self.loss_buf)
-        self.R.backward(self.gimage, None, out=self.grad)
+        self.R.backward_mse(self.target, None, out=self.grad, accumulate=self.accumulate)
         capi.dbmp_adam_step(st, self.params, self.grad, self.m, self.v, self.params.numel(),
-                            self.lr, self.betas[0], self.betas[1], self.eps, self.step_count)
+                            self.lr, self.betas[0], self.betas[1], self.eps, self.step_count,
+                            zero_grad=1 if self.accumulate else 0)
 
     def _size(self):
-        """Render once synchronously and size the pair buffer with headroom."""
-        self.R.render(self.params, self.atlas_idx, self.atlas, self.H, self.W, self.bg,
+        """Store the atlas, render once synchronously and size the tile lists with headroom."""
+        self.R.set_atlas(self.atlas)
+        self.R.render(self.params, self.atlas_idx, None, self.H, self.W, self.bg,
                       self.alpha_max, self.tile, image=self.image, with_alpha=False)
         rc = capi.dbmp_check(self.R.ctx, capi.stream_handle())
-        need = self.R.pair_count()
-        capi.dbmp_reserve(self.R.ctx, int(need * self.headroom) + 4096)
+        need = self.R.longest_list()
+        capi.dbmp_reserve(self.R.ctx, int(need * self.headroom) + 1)
         if rc not in (capi.DBMP_OK, capi.DBMP_EOVERFLOW):
             raise capi.DbmpError(rc, capi.dbmp_last_error(self.R.ctx))
         self._sized = True
@@ -71,7 +74,7 @@ class Fitter:
             self._enqueue()
 
     def _state(self):
-        return [self.params, self.m, self.v, self.step_count]
+        return [self.params, self.m, self.v, self.step_count, self.grad]
 
     def snapshot(self):
         return [t.clone() for t in self._state()]
@@ -112,8 +115,8 @@ class Fitter:
             rc = capi.dbmp_check(self.R.ctx, capi.stream_handle())
             if rc == capi.DBMP_EOVERFLOW:
                 self.restore(snap)
-                need = self.R.pair_count()
-                capi.dbmp_reserve(self.R.ctx, int(need * self.headroom) + 4096)
+                need = self.R.longest_list()
+                capi.dbmp_reserve(self.R.ctx, int(need * max(self.headroom, 1.25)) + 1)
                 if self.graph is not None:
                     self.graph = None
                     self.capture()
@@ -131,7 +134,8 @@ class Fitter:
             raise capi.DbmpError(rc, capi.dbmp_last_error(self.R.ctx))
 
     def loss(self):
-        """MSE of the last rendered image (synchronises)."""
+        """MSE of the image of the last step (before its Adam update; synchronises)."""
+        self.R.mse_loss(self.loss_buf)
         return float(self.loss_buf[0].item()) / self.image.numel()
 
     def psnr(self):

@@ -32,14 +32,14 @@ def _need(t, name, dtype=None, shape=None):
 
 
 class Renderer:
-    """One dbmp context. `check=True` synchronises after each forward to detect a full pair
-    buffer, grows it and renders again; `check=False` keeps every call asynchronous (for graph
-    capture) and leaves overflow to an explicit `check()`."""
+    """One dbmp context. `check=True` synchronises after each forward to detect a tile list
+    that did not fit, grows the capacity and renders again; `check=False` keeps every call
+    asynchronous (for graph capture) and leaves overflow to an explicit `check()`."""
 
-    def __init__(self, device=None, pair_capacity: int = 0, check: bool = True):
+    def __init__(self, device=None, list_capacity: int = 0, check: bool = True):
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.device = dev
-        self.ctx = capi.dbmp_create(dev.index, pair_capacity)
+        self.ctx = capi.dbmp_create(dev.index, list_capacity)
         self.check_each = check
         self.generation = 0
 
@@ -52,18 +52,33 @@ class Renderer:
                 pass
             self.ctx = None
 
+    # -- atlas -------------------------------------------------------------------------------
+    def set_atlas(self, atlas):
+        """Pads and stores the bitmaps once; later renders may pass atlas=None."""
+        if atlas.dim() == 2:
+            atlas = atlas[None]
+        _need(atlas, "atlas")
+        B, Hb, Wb = atlas.shape
+        capi.dbmp_set_atlas(self.ctx, capi.stream_handle(), atlas, B, Hb, Wb, _dtype_code(atlas))
+
     # -- forward -----------------------------------------------------------------------------
     def render(self, params, atlas_idx, atlas, H, W, bg=None, alpha_max=1.0, tile=16,
                image=None, alpha=None, with_alpha=True):
+        """atlas=None renders with the atlas stored by set_atlas (or the previous render)."""
         _need(params, "params", torch.float32)
         N = params.shape[0]
         if params.dim() != 2 or params.shape[1] != 8:
             raise ValueError("params must be [N, 8]")
         _need(atlas_idx, "atlas_idx", torch.int32, (N,))
-        if atlas.dim() == 2:
-            atlas = atlas[None]
-        _need(atlas, "atlas")
-        B, Hb, Wb = atlas.shape
+        if atlas is None:
+            B = Hb = Wb = 0
+            dcode = 0
+        else:
+            if atlas.dim() == 2:
+                atlas = atlas[None]
+            _need(atlas, "atlas")
+            B, Hb, Wb = atlas.shape
+            dcode = _dtype_code(atlas)
         if bg is None:
             bg = torch.ones(3, device=params.device, dtype=torch.float32)
         _need(bg, "bg", torch.float32)
@@ -81,14 +96,14 @@ class Renderer:
         if alpha is not None:
             _need(alpha, "alpha", torch.float32, (H, W))
         st = capi.stream_handle()
-        args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, _dtype_code(atlas), H, W,
+        args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, dcode, H, W,
                 bg, bg_pp, alpha_max, tile, image, alpha)
         capi.dbmp_render(*args)
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
             if rc == capi.DBMP_EOVERFLOW:
-                need = capi.dbmp_pair_count(self.ctx, st)
-                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 4096)
+                need = capi.dbmp_longest_list(self.ctx, st)
+                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 16)
                 capi.dbmp_render(*args)
                 rc = capi.dbmp_check(self.ctx, st)
             if rc != capi.DBMP_OK:
@@ -118,8 +133,8 @@ class Renderer:
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
             if rc == capi.DBMP_EOVERFLOW:
-                need = capi.dbmp_pair_count(self.ctx, st)
-                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 4096)
+                need = capi.dbmp_longest_list(self.ctx, st)
+                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 16)
                 capi.dbmp_render_batched(*args)
                 rc = capi.dbmp_check(self.ctx, st)
             if rc != capi.DBMP_OK:
@@ -137,13 +152,30 @@ class Renderer:
         capi.dbmp_render_backward(self.ctx, capi.stream_handle(), dL_dimage, dL_dalpha, out)
         return out
 
+    def backward_mse(self, target, dL_dalpha=None, n_params=None, out=None, accumulate=False):
+        """Backward of L = mean((I - target)^2) (+ any dL/dA) for the last forward; the gradient
+        of the loss w.r.t. the image is formed inside the kernel. accumulate=True adds into out."""
+        _need(target, "target", torch.float32)
+        if dL_dalpha is not None:
+            _need(dL_dalpha, "dL_dalpha", torch.float32)
+        if out is None:
+            out = torch.empty(n_params, 8, device=target.device, dtype=torch.float32)
+        capi.dbmp_render_backward_mse(self.ctx, capi.stream_handle(), target, dL_dalpha, out,
+                                      1 if accumulate else 0)
+        return out
+
+    def mse_loss(self, out):
+        """Per-image sum of squared errors of the last backward_mse into out (device)."""
+        capi.dbmp_mse_loss(self.ctx, capi.stream_handle(), out)
+        return out
+
     def check(self):
         rc = capi.dbmp_check(self.ctx, capi.stream_handle())
         if rc != capi.DBMP_OK:
             raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
 
-    def pair_count(self):
-        return capi.dbmp_pair_count(self.ctx, capi.stream_handle())
+    def longest_list(self):
+        return capi.dbmp_longest_list(self.ctx, capi.stream_handle())
 
 
 class RenderFn(torch.autograd.Function):

@@ -18,7 +18,9 @@ def test_header_declares_the_boundary():
     names = header_functions()
     for n in ["dbmp_create", "dbmp_destroy", "dbmp_render", "dbmp_render_backward",
               "dbmp_render_batched", "dbmp_check", "dbmp_last_error", "dbmp_mse_grad",
-              "dbmp_adam_step", "dbmp_reserve", "dbmp_pair_count"]:
+              "dbmp_adam_step", "dbmp_reserve", "dbmp_longest_list",
+              "dbmp_render_backward_mse", "dbmp_mse_loss", "dbmp_support_pairs",
+              "dbmp_set_atlas"]:
         assert n in names
 
 
@@ -36,10 +38,14 @@ def test_host_argument_checks_need_no_device():
     assert lib.dbmp_mse_grad(None, None, None, -1, None, None) == capi.DBMP_EINVAL
     assert lib.dbmp_mse_grad(None, None, None, 0, None, None) == capi.DBMP_OK
     assert lib.dbmp_adam_step(None, None, None, None, None, 4, 1e-2, 0.9, 0.999, 1e-8,
-                              None) == capi.DBMP_EINVAL
+                              None, 0) == capi.DBMP_EINVAL
     assert lib.dbmp_check(None, None) == capi.DBMP_EINVAL
     assert lib.dbmp_reserve(None, 10) == capi.DBMP_EINVAL
     assert lib.dbmp_destroy(None) == capi.DBMP_EINVAL
     assert lib.dbmp_last_error(None) == b"null context"
+    assert lib.dbmp_render_backward_mse(None, None, None, None, None, 0) == capi.DBMP_EINVAL
+    assert lib.dbmp_set_atlas(None, None, None, 1, 2, 2, 0) == capi.DBMP_EINVAL
+    assert lib.dbmp_mse_loss(None, None, None) == capi.DBMP_EINVAL
+    assert lib.dbmp_longest_list(None, None) == -1
     h = ctypes.c_void_p()
     assert lib.dbmp_create(ctypes.byref(h), 0, -5) == capi.DBMP_EINVAL

@@ -259,7 +259,7 @@ def test_long_tile_lists_all_sort_paths(R):
         Rl = Renderer()
         img, _, _ = gpu_render(Rl, p, i_t, a, H, W, (1, 1, 1), tile=tile)
         assert img_err(img.cpu(), ref) <= IMG_TOL
-    assert Rl.pair_count() > 2048  # at tile 32 the whole canvas is 4 tiles of ~3000 entries
+    assert Rl.longest_list() > 2048  # at tile 32 the whole canvas is 4 tiles of ~3000 entries
 
 
 def test_device_errors_are_flagged(R):
@@ -284,17 +284,17 @@ def test_device_errors_are_flagged(R):
         R.render(p, idx, a, 128, 128, bg, 1.0, 12)
 
 
-def test_pair_buffer_overflow_is_reported_then_grown():
+def test_list_overflow_is_reported_then_grown():
     from paper_2602_22625_amd import capi
     from paper_2602_22625_amd.render import Renderer
     d = synth.make_workload("c1")
     p, idx, a = to_dev(d)
-    small = Renderer(pair_capacity=1000, check=False)
+    small = Renderer(list_capacity=8, check=False)
     bg = torch.ones(3, device="cuda")
     small.render(p, idx, a, 512, 512, bg, 1.0, 16)
     assert capi.dbmp_check(small.ctx, capi.stream_handle()) == capi.DBMP_EOVERFLOW
-    need = small.pair_count()
-    assert need > 1000
+    need = small.longest_list()
+    assert need > 8
     capi.dbmp_reserve(small.ctx, need)
     img, _ = small.render(p, idx, a, 512, 512, bg, 1.0, 16)
     small.check()
@@ -348,3 +348,18 @@ def test_autograd_function_matches_oracle(R):
     gA = np.full((128, 128), 0.5 / (128 * 128))
     gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], 128, 128, gI, gA)
     assert_grads(p.grad.cpu().numpy(), gref)
+
+
+def test_stored_atlas_equals_per_call_atlas():
+    """dbmp_set_atlas once + renders with atlas=NULL == renders given the atlas (bitwise)."""
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c1")
+    p, idx, a = to_dev(d)
+    R1, R2 = Renderer(), Renderer()
+    R2.set_atlas(a)
+    for k in range(3):
+        q = p + 0.37 * k
+        i1, a1 = R1.render(q, idx, a, 512, 512, None, 1.0, 16)
+        i2, a2 = R2.render(q, idx, None, 512, 512, None, 1.0, 16)
+        torch.cuda.synchronize()
+        assert torch.equal(i1, i2) and torch.equal(a1, a2)
