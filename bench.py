@@ -157,7 +157,8 @@ def main():
         A2 = torch.tensor(d2["atlas_bf16"].view(np.int16), device=dev).view(torch.bfloat16)
         T2 = torch.tensor(d2["target"], device=dev)
         R2 = Renderer(device=0)
-        img2, _ = R2.render(P2, I2, A2, wl2.H, wl2.W, None, 1.0, wl2.tile, with_alpha=False)
+        R2.set_atlas(A2)  # the templates are constant during a fit: stored once
+        img2, _ = R2.render(P2, I2, None, wl2.H, wl2.W, None, 1.0, wl2.tile, with_alpha=False)
         g2 = torch.empty_like(img2)
         capi.dbmp_mse_grad(capi.stream_handle(), img2, T2, img2.numel(), g2, None)
         R2.check_each = False
@@ -168,7 +169,7 @@ def main():
         for k in range(reps + 2):
             e = ev2[k - 2] if k >= 2 else None
             if e: e[0].record(st)
-            R2.render(P2, I2, A2, wl2.H, wl2.W, None, 1.0, wl2.tile, image=img2,
+            R2.render(P2, I2, None, wl2.H, wl2.W, None, 1.0, wl2.tile, image=img2,
                       with_alpha=False)
             if e: e[1].record(st)
             R2.backward(g2, None, out=out2)
@@ -239,14 +240,13 @@ def profile_driver(args, synth, capi, Renderer, np, torch, dev):
         A = torch.tensor(d["atlas"], device=dev)
     T = torch.tensor(d["target"], device=dev)
     R = Renderer(device=0)
-    img, _ = R.render(P, I, A, wl.H, wl.W, None, 1.0, wl.tile, with_alpha=False)
-    g = torch.empty_like(img)
-    capi.dbmp_mse_grad(capi.stream_handle(), img, T, img.numel(), g, None)
+    R.set_atlas(A)
+    img, _ = R.render(P, I, None, wl.H, wl.W, None, 1.0, wl.tile, with_alpha=False)
     R.check_each = False
-    out = torch.empty(wl.N, 8, device=dev)
+    out = torch.zeros(wl.N, 8, device=dev)
     for k in range(args.steps):
-        R.render(P, I, A, wl.H, wl.W, None, 1.0, wl.tile, image=img, with_alpha=False)
-        R.backward(g, None, out=out)
+        R.render(P, I, None, wl.H, wl.W, None, 1.0, wl.tile, image=img, with_alpha=False)
+        R.backward_mse(T, None, out=out, accumulate=True)
     torch.cuda.synchronize()
     R.check()
     src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -254,7 +254,7 @@ def profile_driver(args, synth, capi, Renderer, np, torch, dev):
     torch.cuda.synchronize()
     dst.copy_(src)  # 256 MiB read + 256 MiB write
     torch.cuda.synchronize()
-    log("profile driver: %s, %d forward+backward passes, then a 256 MiB copy" %
+    log("profile driver: %s, %d forward+backward(MSE) passes, then a 256 MiB copy" %
         (args.profile, args.steps))
 
 

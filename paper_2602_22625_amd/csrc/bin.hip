@@ -137,8 +137,10 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
         rec.ccr = rec.ccg = rec.ccb = 0.f;
         rec.faU = rec.fbU = rec.faV = rec.fbV = 0.f;
         rec.tx0 = 1; rec.tx1 = 0; rec.ty0 = 1; rec.ty1 = 0;
+        rec.px0 = 1; rec.px1 = 0; rec.py0 = 1; rec.py1 = 0;
         rec.img = rec.tile_off = rec.ntx = rec.W = rec.H = 0;
-        rec.pad[0] = rec.pad[1] = 0;
+        rec.id = (int)g;
+        rec.pad = 0;
         if (g < n_rows) {
             const int b = find_by_prim(imgs, n_images, g);
             const ImgDev D = imgs[b];
@@ -218,8 +220,10 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
                         const double fy0 = fmax(ceil(ymin - mg), 0.0);
                         const double fy1 = fmin(floor(ymax + mg), D.H - 1.0);
                         if (fx0 <= fx1 && fy0 <= fy1) {
-                            rec.tx0 = (int)fx0 / TS; rec.tx1 = (int)fx1 / TS;
-                            rec.ty0 = (int)fy0 / TS; rec.ty1 = (int)fy1 / TS;
+                            rec.px0 = (int)fx0; rec.px1 = (int)fx1;
+                            rec.py0 = (int)fy0; rec.py1 = (int)fy1;
+                            rec.tx0 = rec.px0 / TS; rec.tx1 = rec.px1 / TS;
+                            rec.ty0 = rec.py0 / TS; rec.ty1 = rec.py1 / TS;
                         }
                     }
                 }

@@ -99,6 +99,10 @@ int ensure(dbmp_ctx *c, Buf &b, size_t bytes, hipStream_t st, const char *what)
     return DBMP_OK;
 }
 
+// List capacities are kept a multiple of 32 entries so every tile's list starts on its own
+// 128-byte line (no two tiles share a cache line of list entries).
+int round_cap(int c) { return (c + 31) & ~31; }
+
 bool same_imgs(const std::vector<ImgDev> &a, const std::vector<ImgDev> &b)
 {
     if (a.size() != b.size()) return false;
@@ -277,7 +281,7 @@ int dbmp_create(dbmp_ctx **out, int device, long long list_capacity)
     dbmp_ctx *c = new (std::nothrow) dbmp_ctx();
     if (!c) return DBMP_ENOMEM;
     c->device = device;
-    c->list_cap = list_capacity > 0 ? (int)list_capacity : 256;
+    c->list_cap = round_cap(list_capacity > 0 ? (int)list_capacity : 256);
     DeviceGuard g(device);
     int rc = ensure(c, c->flags, 4 * F_COUNT, nullptr, "flags");
     if (!rc) rc = ensure(c, c->counter, 8 * DBMP_COUNTER_SLOTS, nullptr, "counter");
@@ -315,7 +319,7 @@ int dbmp_reserve(dbmp_ctx *c, long long list_capacity)
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
     if (list_capacity > c->list_cap) {
-        c->list_cap = (int)list_capacity;  // the list buffer grows at the next forward
+        c->list_cap = round_cap((int)list_capacity);  // the buffer grows at the next forward
         c->have_fwd = false;               // the lists of the last forward are stale
     }
     e = hipMemset(c->list_max.p, 0, 4 * DBMP_COUNTER_SLOTS);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stddef.h>
 
 namespace dbmp {
 
@@ -42,17 +43,20 @@ struct __attribute__((aligned(16))) PrimRec {
     double aU, bU, eU;
     double aV, bV, eV;
     double Ulo, Uhi, Vlo, Vhi;  // M is non-zero only for Ulo <= U' < Uhi and Vlo <= V' < Vhi
+    int px0, px1, py0, py1;     // pixel bounding box of that region (empty: px0 > px1)
     float ka;                   // alpha_max * sigmoid(nu)
     float cr, cg, cb;           // sigmoid of the colour logits
     int tex;                    // element offset of the padded bitmap's (0, 0)
     float kaom;                 // alpha_max * sigmoid(nu) * (1 - sigmoid(nu))  (d alpha / d nu / M)
     float ccr, ccg, ccb;        // c (1 - c): derivative of the colour sigmoid
     float faU, fbU, faV, fbV;   // float copies of the map's linear part (backward chain rule)
-    int tx0, tx1, ty0, ty1;     // tile span of the support's bounding box (empty: tx0 > tx1)
+    int tx0, tx1, ty0, ty1;     // tile span of the bounding box (empty: tx0 > tx1)
     int img, tile_off, ntx, W, H;  // the primitive's image: first tile, tiles per row, size
-    int pad[2];
+    int id;                     // the primitive's row in params
+    int pad;
 };
-static_assert(sizeof(PrimRec) == 176, "PrimRec layout");
+static_assert(sizeof(PrimRec) == 192, "PrimRec layout");
+static_assert(offsetof(PrimRec, px0) == 80, "the pixel box is read as one 16-byte vector");
 
 __device__ __forceinline__ int find_by_prim(const ImgDev *__restrict__ imgs, int n, long long g)
 {

@@ -2,8 +2,8 @@
 //
 // One workgroup per T x T screen tile, one lane per pixel, the tile's wave64s laid out as 8 x 8
 // pixel blocks (the most compact footprint, so whole waves skip primitives they do not touch).
-// Each wave walks the tile's primitive list; the primitive record is wave-uniform and is read
-// through the scalar cache, so the inverse-affine coefficients sit in SGPRs. Texels are fetched
+// The tile's list is walked in batches of 64 entries whose records the workgroup first copies to
+// LDS; each wave then visits only the entries whose pixel box overlaps its block. Texels are fetched
 // from the zero-bordered atlas copy (L1/L2): at these workloads a primitive is minified 2-8x,
 // so staging its footprint in LDS would move many more texels than the 4 each pixel samples.
 //
@@ -43,6 +43,7 @@ struct TileGeom {
     bool valid;
     ImgDev D;
     int b;
+    int bx0, by0;  // origin of this wave's 8 x 8 pixel block (wave-uniform)
 };
 
 template <int TS>
@@ -55,12 +56,46 @@ __device__ __forceinline__ TileGeom<TS> tile_geom(int tile, const ImgDev *__rest
     const int lt = tile - tg.D.tile_off;
     const int tx = lt % tg.D.ntx, ty = lt / tg.D.ntx;
     constexpr int WPR = TS / 8;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    tg.px = tx * TS + (wave % WPR) * 8 + (lane & 7);
-    tg.py = ty * TS + (wave / WPR) * 8 + (lane >> 3);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    tg.bx0 = tx * TS + (wave % WPR) * 8;
+    tg.by0 = ty * TS + (wave / WPR) * 8;
+    tg.px = tg.bx0 + (lane & 7);
+    tg.py = tg.by0 + (lane >> 3);
     tg.valid = tg.px < tg.D.W && tg.py < tg.D.H;
     tg.pix = tg.py * tg.D.W + tg.px;
     return tg;
+}
+
+// List entries are processed in batches of 64: the workgroup copies the batch's records into LDS
+// with coalesced 16-byte loads (independent, so their latencies overlap), then every wave marks
+// with one ballot the entries whose pixel box overlaps its 8 x 8 block (lane e tests entry e)
+// and visits only those, reading the record from LDS.
+constexpr int BATCH = 64;
+constexpr int RQ = sizeof(PrimRec) / 16;
+
+template <int NT, typename IdAt>
+__device__ __forceinline__ void stage_batch(PrimRec *__restrict__ s_rec,
+                                            const PrimRec *__restrict__ recs, int b0, int cnt,
+                                            IdAt id_at)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(recs);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_rec);
+    for (int q = threadIdx.x; q < cnt * RQ; q += NT) {
+        const int e = q / RQ;
+        dst[q] = src[(size_t)id_at(b0 + e) * RQ + (q - e * RQ)];
+    }
+}
+
+__device__ __forceinline__ uint64_t batch_hits(const PrimRec *__restrict__ s_rec, int cnt, int bx0,
+                                               int by0)
+{
+    const int e = threadIdx.x & 63;
+    bool hit = false;
+    if (e < cnt) {
+        const int4 bb = *reinterpret_cast<const int4 *>(&s_rec[e].px0);  // px0, px1, py0, py1
+        hit = bb.y >= bx0 && bb.x <= bx0 + 7 && bb.w >= by0 && bb.z <= by0 + 7;
+    }
+    return __ballot(hit);
 }
 
 // Lanes of the wave whose pixel lies in the primitive's support: four float64 compares whose
@@ -177,31 +212,41 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, TK = 1.f;
     int K = -1;
     unsigned long long npairs = 0;  // wave-uniform count of evaluated (pixel, primitive) pairs
+    __shared__ PrimRec s_rec[BATCH];
     auto composite = [&](auto id_at) {
-        for (int j = 0; j < n; ++j) {
-            const PrimRec &r = recs[id_at(j)];
-            const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-            const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-            const uint64_t m = support_mask(r, U, V, vmask);
-            if (m == 0) continue;  // no lane of this wave touches the primitive
-            npairs += __popcll(m);
-            if (__builtin_amdgcn_inverse_ballot_w64(m)) {
-                float M, MU, MV;
-                bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
-                const float a = r.ka * M;  // Eq. (3)
-                if (T >= DBMP_TAU) { K = j; TK = T; }
-                const float w = T * a;
-                C0 = fmaf(w, r.cr, C0);
-                C1 = fmaf(w, r.cg, C1);
-                C2 = fmaf(w, r.cb, C2);
-                T = T * (1.f - a);
+        for (int b0 = 0; b0 < n; b0 += BATCH) {
+            const int cnt = min(BATCH, n - b0);
+            __syncthreads();  // the previous batch is consumed (first pass: the sort is done)
+            stage_batch<NT>(s_rec, recs, b0, cnt, id_at);
+            __syncthreads();
+            uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
+            while (hits) {  // ascending list order: front to back
+                const int e = __builtin_ctzll(hits);
+                hits &= hits - 1;
+                const PrimRec &r = s_rec[e];
+                const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+                const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+                const uint64_t m = support_mask(r, U, V, vmask);
+                if (m == 0) continue;  // no lane of this wave touches the primitive
+                npairs += __popcll(m);
+                if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+                    float M, MU, MV;
+                    bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
+                    const float a = r.ka * M;  // Eq. (3)
+                    if (T >= DBMP_TAU) { K = b0 + e; TK = T; }
+                    const float w = T * a;
+                    C0 = fmaf(w, r.cr, C0);
+                    C1 = fmaf(w, r.cg, C1);
+                    C2 = fmaf(w, r.cb, C2);
+                    T = T * (1.f - a);
+                }
             }
         }
     };
     if (in_lds)
-        composite([&](int j) { return __builtin_amdgcn_readfirstlane(s_ids[j]); });
+        composite([&](int j) { return s_ids[j]; });
     else
-        composite([&](int j) { return __builtin_amdgcn_readfirstlane(((volatile int *)seg)[j]); });
+        composite([&](int j) { return ((volatile int *)seg)[j]; });
     if ((threadIdx.x & 63) == 0 && npairs)  // spread over slots: no single hot address
         atomicAdd(pair_counter + ((blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) &
                                   (DBMP_COUNTER_SLOTS - 1)),
@@ -329,53 +374,61 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
     }
     float Bk = 1.f, Trun = TK;
     const int *seg = lists + (size_t)tile * list_cap;
-    int gnext = n > 0 ? seg[n - 1] : 0;
-    for (int j = n - 1; j >= 0; --j) {
-        const int g = gnext;
-        if (j > 0) gnext = seg[j - 1];  // next id, loaded while this one is processed
-        const PrimRec &r = recs[g];
-        const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-        const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-        const uint64_t msk = support_mask(r, U, V, vmask);
-        if (msk == 0) continue;
-        float d[8];
+    __shared__ PrimRec s_rec[BATCH];
+    for (int hi = n; hi > 0; hi -= BATCH) {
+        const int b0 = max(0, hi - BATCH), cnt = hi - b0;
+        __syncthreads();  // the previous batch is consumed
+        stage_batch<TS * TS>(s_rec, recs, b0, cnt, [&](int j) { return seg[j]; });
+        __syncthreads();
+        uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
+        while (hits) {  // descending list order: back to front
+            const int e = 63 - __builtin_clzll(hits);
+            hits ^= 1ull << e;
+            const PrimRec &r = s_rec[e];
+            const int j = b0 + e;
+            const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+            const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+            const uint64_t msk = support_mask(r, U, V, vmask);
+            if (msk == 0) continue;
+            float d[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) d[q] = 0.f;
-        if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
-            float M, MU, MV;
-            bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
-            const float a = r.ka * M;
-            const float m = 1.f - a;
-            // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
-            float rc = __builtin_amdgcn_rcpf(m);
-            rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
-            const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
-            Trun = Tj;
-            const float cr = r.cr, cg = r.cg, cb = r.cb;
-            float dal = g0 * (cr - G0);
-            dal = fmaf(g1, cg - G1, dal);
-            dal = fmaf(g2, cb - G2, dal);
-            if (HAS_GA) dal = fmaf(ga, Bk, dal);
-            dal *= Tj;
-            const float ta = Tj * a;
-            d[5] = g0 * ta * r.ccr;
-            d[6] = g1 * ta * r.ccg;
-            d[7] = g2 * ta * r.ccb;
-            d[4] = dal * r.kaom * M;
-            const float dM = dal * r.ka;
-            const float gU = dM * MU, gV = dM * MV;
-            const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
-            d[0] = -fmaf(gU, r.faU, gV * r.faV);
-            d[1] = -fmaf(gU, r.fbU, gV * r.fbV);
-            d[2] = -fmaf(gU, Ub, gV * Vb);
-            d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
-            G0 = fmaf(m, G0, a * cr);
-            G1 = fmaf(m, G1, a * cg);
-            G2 = fmaf(m, G2, a * cb);
-            Bk *= m;
+            for (int q = 0; q < 8; ++q) d[q] = 0.f;
+            if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
+                float M, MU, MV;
+                bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
+                const float a = r.ka * M;
+                const float m = 1.f - a;
+                // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
+                float rc = __builtin_amdgcn_rcpf(m);
+                rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
+                const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
+                Trun = Tj;
+                const float cr = r.cr, cg = r.cg, cb = r.cb;
+                float dal = g0 * (cr - G0);
+                dal = fmaf(g1, cg - G1, dal);
+                dal = fmaf(g2, cb - G2, dal);
+                if (HAS_GA) dal = fmaf(ga, Bk, dal);
+                dal *= Tj;
+                const float ta = Tj * a;
+                d[5] = g0 * ta * r.ccr;
+                d[6] = g1 * ta * r.ccg;
+                d[7] = g2 * ta * r.ccb;
+                d[4] = dal * r.kaom * M;
+                const float dM = dal * r.ka;
+                const float gU = dM * MU, gV = dM * MV;
+                const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
+                d[0] = -fmaf(gU, r.faU, gV * r.faV);
+                d[1] = -fmaf(gU, r.fbU, gV * r.fbV);
+                d[2] = -fmaf(gU, Ub, gV * Vb);
+                d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
+                G0 = fmaf(m, G0, a * cr);
+                G1 = fmaf(m, G1, a * cg);
+                G2 = fmaf(m, G2, a * cb);
+                Bk *= m;
+            }
+            const float tot = reduce8(d, lane);
+            if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
         }
-        const float tot = reduce8(d, lane);
-        if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)g * 8 + (lane >> 3), tot);
     }
     if (MSE) {
         __shared__ float s_loss[TS * TS / 64];

@@ -69,7 +69,26 @@ def support_pairs(params, Hb, Wb, H, W, crop=None, idx=None, boxes=None):
     return total
 
 
-# Per support pair arithmetic of the method (float operations, an FMA counted as 2), used for
-# the algorithmic-work side of the roofline. Derivation in the design notes.
-FWD_FLOP_PER_PAIR = 32
-BWD_FLOP_PER_PAIR = 90
+# Arithmetic the method performs per evaluated (pixel, primitive) pair, in floating-point
+# operations (an FMA counts 2; floor/fraction and the reciprocal count 1 each), for the
+# algorithmic side of the roofline. Culling tests, addressing and loop control are excluded.
+FWD_FLOP_PER_PAIR = (
+    8      # Eq. (1)-(2): U', V' = a x + b y + e, two FMAs each
+    + 4    # integer part and fraction of U', V'
+    + 9    # Supp. Eqs. (S1)-(S3): two differences, three lerps (FMA) and one difference
+    + 1    # Eq. (3): alpha = alpha_max sigma(nu) M
+    + 1    # w = T alpha
+    + 6    # Eq. (5): C += w c, three FMAs
+    + 2    # Eq. (4): T *= (1 - alpha)
+)  # = 31
+BWD_FLOP_PER_PAIR = (
+    8 + 4 + 12  # coordinates, fraction, bilinear value and both derivatives
+    + 3         # alpha, 1 - alpha, T_j = T_{j+1} / (1 - alpha_j)
+    + 12        # Supp. Eq. (S5): g . (c - G) + g_A B, times T_j
+    + 7         # Supp. Eq. (S4): T alpha, then g_c (T alpha) c (1 - c) per channel
+    + 3         # dL/dnu and dL/dM
+    + 4         # dL/dU', dL/dV' and the centred coordinates
+    + 14        # Eq. (7): x, y, log s, theta
+    + 10        # back-to-front recurrences G and B
+    + 8         # summing the 8 partials over pixels
+)  # = 85
