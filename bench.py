@@ -31,6 +31,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_digest():
+    """sha256 over the raster kernels' sources: identifies the code the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("raster.hip", "dbmp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2602_22625_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, scaled by the
+    copy-kernel calibration it records; None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,37 +118,51 @@ def main():
     value = pairs_timed / wall
     log("graph steps: %.3f ms/step, %.3e evals/s, psnr %.2f" % (ms_per_step, value, fit.psnr()))
 
-    # ---------------- per-kernel durations: eager steps with HIP events on the stream ----------
+    # ---------------- per-kernel durations: HIP events on the launch stream -----------------------
+    # Each kernel is launched `reps` times back to back between one pair of events, so the event
+    # overhead is amortised and the average matches the profiler's per-dispatch duration.
     R = fit.R
+    R.check_each = False
     st = torch.cuda.current_stream()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        e = evs[k]
-        e[0].record(st)
+    reps = max(args.steps, 20)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    def fwd():
         R.render(fit.params, idx, None, H, W, fit.bg, 1.0, wl.tile, image=fit.image,
                  with_alpha=False)
-        e[1].record(st)
+
+    def bwd():
         R.backward_mse(fit.target, None, out=fit.grad, accumulate=True)
-        e[2].record(st)
+
+    def adam():
         capi.dbmp_adam_step(capi.stream_handle(), fit.params, fit.grad, fit.m, fit.v,
                             fit.params.numel(), 1e-2, 0.9, 0.999, 1e-8, fit.step_count,
                             zero_grad=1)
-        e[3].record(st)
-    torch.cuda.synchronize()
-    fit.check()
-    pairs_eager = capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1)
-    t_fwd = np.mean([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
-    t_bwd = np.mean([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
-    t_adam = np.mean([e[2].elapsed_time(e[3]) for e in evs]) * 1e-3
-    ppl = pairs_eager / args.steps  # evaluated pairs per forward (= per backward)
+
+    snap = fit.snapshot()
+    capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1)
+    t_fwd = timed(fwd)
+    R.check()
+    ppl = capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1) / (reps + 1)
+    t_bwd = timed(bwd)
+    t_adam = timed(adam)
+    fit.restore(snap)
     bwd_flops = ppl * metrics.BWD_FLOP_PER_PAIR
     bwd_tflops = bwd_flops / t_bwd * 1e-12
-    log("eager: fwd(bin+raster) %.1f us, bwd(+mse) %.1f us, adam %.1f us, pairs %.0f"
+    log("per launch: fwd(bin+raster) %.1f us, bwd(+mse) %.1f us, adam %.1f us, pairs %.0f"
         % (t_fwd * 1e6, t_bwd * 1e6, t_adam * 1e6, ppl))
-    # algorithmic HBM bytes of the backward launch: image and target (24 B/px) + per-pixel state
-    # (8 B/px) + records + dL/dparams accumulation; see the design notes
     longest = R.longest_list()
-    bwd_bytes = 24 * H * W + 8 * H * W + 176 * N + 64 * N + atlas.numel() * 4
+    bwd_bytes = metrics.bwd_algorithmic_bytes(H, W, N, atlas.numel() * 4)
+    traffic = measured_traffic("k_raster_bwd_512sq_4096prims_traffic.md")
     roofline = {
         "kernel": "k_raster_bwd (MSE gradient fused, accumulating into the zeroed gradient)",
         "bound": "alu",
@@ -133,16 +174,17 @@ def main():
         "flop_per_pair": metrics.BWD_FLOP_PER_PAIR,
         "pairs_per_launch": round(ppl),
         "avg_launch_us": round(t_bwd * 1e6, 2),
+        "hbm_algorithmic_bytes": round(bwd_bytes),
         "hbm_algorithmic_GBps": round(bwd_bytes / t_bwd * 1e-9, 2),
         "hbm_frac": round(bwd_bytes / t_bwd * 1e-9 / PEAK_HBM_GBS, 5),
-        "traffic": None,
+        "traffic": traffic,
     }
 
     extra = {
         "adam_iters_per_s_graph": round(args.steps / wall, 2),
-        "eager_breakdown_us": {"fwd_incl_binning": round(t_fwd * 1e6, 2),
-                               "bwd_incl_mse": round(t_bwd * 1e6, 2),
-                               "adam": round(t_adam * 1e6, 2)},
+        "per_launch_us": {"fwd_incl_binning": round(t_fwd * 1e6, 2),
+                          "bwd_incl_mse": round(t_bwd * 1e6, 2),
+                          "adam": round(t_adam * 1e6, 2)},
         "fwd_plus_bwd_evals_per_s_eager": round(ppl / (t_fwd + t_bwd)),
         "psnr_after_steps": round(fit.psnr(), 3),
         "longest_tile_list": int(longest),
@@ -163,22 +205,24 @@ def main():
         capi.dbmp_mse_grad(capi.stream_handle(), img2, T2, img2.numel(), g2, None)
         R2.check_each = False
         out2 = torch.empty(wl2.N, 8, device=dev)
-        reps = 10
-        ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        reps2 = 10
+
+        def timed2(fn):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fn()
+            e0.record(st)
+            for _ in range(reps2):
+                fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e-3 / reps2
+
         capi.dbmp_support_pairs(R2.ctx, capi.stream_handle(), reset=1)
-        for k in range(reps + 2):
-            e = ev2[k - 2] if k >= 2 else None
-            if e: e[0].record(st)
-            R2.render(P2, I2, None, wl2.H, wl2.W, None, 1.0, wl2.tile, image=img2,
-                      with_alpha=False)
-            if e: e[1].record(st)
-            R2.backward(g2, None, out=out2)
-            if e: e[2].record(st)
-        torch.cuda.synchronize()
+        f2 = timed2(lambda: R2.render(P2, I2, None, wl2.H, wl2.W, None, 1.0, wl2.tile,
+                                      image=img2, with_alpha=False))
         R2.check()
-        pp2 = capi.dbmp_support_pairs(R2.ctx, capi.stream_handle(), reset=1) / (reps + 2)
-        f2 = np.median([e[0].elapsed_time(e[1]) for e in ev2]) * 1e-3
-        b2 = np.median([e[1].elapsed_time(e[2]) for e in ev2]) * 1e-3
+        pp2 = capi.dbmp_support_pairs(R2.ctx, capi.stream_handle(), reset=1) / (reps2 + 1)
+        b2 = timed2(lambda: R2.backward(g2, None, out=out2))
         extra["c2_2048sq_65536prims"] = {
             "fwd_incl_binning_ms": round(f2 * 1e3, 4), "bwd_ms": round(b2 * 1e3, 4),
             "evals_per_pass": round(pp2), "fwd_plus_bwd_evals_per_s": round(pp2 / (f2 + b2)),

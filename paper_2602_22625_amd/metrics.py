@@ -92,3 +92,11 @@ BWD_FLOP_PER_PAIR = (
     + 10        # back-to-front recurrences G and B
     + 8         # summing the 8 partials over pixels
 )  # = 85
+
+
+def bwd_algorithmic_bytes(H, W, N, atlas_bytes):
+    """HBM bytes the MSE-fused backward must move: the forward's image and the target (12 B per
+    pixel each), the forward's per-pixel (K, T_K) (8 B), every primitive's 8 parameters in and 8
+    gradients out (32 B each) and the atlas once. Tile list ids (4 B per tile-primitive pair,
+    under 2 % of the total at these workloads) are not counted."""
+    return 32 * H * W + 64 * N + atlas_bytes
