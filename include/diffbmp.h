@@ -72,6 +72,23 @@ int dbmp_destroy(dbmp_ctx *ctx);
 int dbmp_reserve(dbmp_ctx *ctx, long long list_capacity);
 
 /*
+ * Launch schedule of the raster kernels for the following forwards (and the backwards of those
+ * forwards). Results do not depend on it: every tile is computed the same way; only which
+ * workgroup computes it, and when, changes.
+ *   DBMP_SCHED_GRID        one workgroup per screen tile, in image order (default).
+ *   DBMP_SCHED_SORTED      one workgroup per tile, tiles dealt longest list first (a counting
+ *                          sort of the tile list lengths runs after binning).
+ *   DBMP_SCHED_PERSISTENT  workgroups_per_cu x (compute units) workgroups stay resident and take
+ *                          tiles, longest list first, from a device work queue until it is
+ *                          empty: one launch per stage however many images a batch holds.
+ * workgroups_per_cu in [1, 32] (used by DBMP_SCHED_PERSISTENT). Host-only, no synchronisation;
+ * the sorted schedules need a workspace that grows at the next forward (not during graph capture).
+ */
+typedef enum { DBMP_SCHED_GRID = 0, DBMP_SCHED_SORTED = 1, DBMP_SCHED_PERSISTENT = 2 } dbmp_schedule;
+
+int dbmp_set_schedule(dbmp_ctx *ctx, int schedule, int workgroups_per_cu);
+
+/*
  * Stores the bitmap templates in the context: each bitmap is copied with a one-texel zero border
  * (the zero padding of the bilinear sampler) and its bounding box of non-zero texels is found.
  * Renders given atlas == NULL use this copy, so a fit loop pays for it once. A render given an
@@ -132,7 +149,8 @@ int dbmp_render_backward_mse(dbmp_ctx *ctx, dbmp_stream stream, const float *tar
 int dbmp_mse_loss(dbmp_ctx *ctx, dbmp_stream stream, float *out);
 
 /*
- * Batched forward: n_images independent images rendered by one persistent launch per stage.
+ * Batched forward: n_images independent images rendered by one launch per stage (binning, raster;
+ * with DBMP_SCHED_PERSISTENT one resident grid drains all images' tiles).
  * Image i has desc[i] = {H, W, N, prim_offset, pixel_offset}: its primitives are rows
  * [prim_offset, prim_offset + N) of params / atlas_idx, its image occupies
  * image[3 * pixel_offset + c * H * W + y * W + x] and its alpha alpha[pixel_offset + y * W + x].

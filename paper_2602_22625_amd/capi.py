@@ -15,6 +15,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "diffbmp.h")
 DBMP_OK, DBMP_EINVAL, DBMP_ENOMEM, DBMP_EHIP, DBMP_EOVERFLOW, DBMP_ESTATE, DBMP_ENONFINITE = \
     0, -1, -2, -3, -4, -5, -6
 DBMP_F32, DBMP_BF16 = 0, 1
+DBMP_SCHED_GRID, DBMP_SCHED_SORTED, DBMP_SCHED_PERSISTENT = 0, 1, 2
 STATUS_NAMES = {0: "DBMP_OK", -1: "DBMP_EINVAL", -2: "DBMP_ENOMEM", -3: "DBMP_EHIP",
                 -4: "DBMP_EOVERFLOW", -5: "DBMP_ESTATE", -6: "DBMP_ENONFINITE"}
 
@@ -50,6 +51,7 @@ def load():
         "dbmp_create": ([ctypes.POINTER(P), I, LL], I),
         "dbmp_destroy": ([P], I),
         "dbmp_reserve": ([P, LL], I),
+        "dbmp_set_schedule": ([P, I, I], I),
         "dbmp_set_atlas": ([P, P, P, I, I, I, I], I),
         "dbmp_render": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P], I),
         "dbmp_render_backward": ([P, P, P, P, P], I),
@@ -108,6 +110,10 @@ def dbmp_destroy(ctx):
 
 def dbmp_reserve(ctx, list_capacity):
     return _chk(ctx, load().dbmp_reserve(ctx, int(list_capacity)))
+
+
+def dbmp_set_schedule(ctx, schedule, workgroups_per_cu=4):
+    return _chk(ctx, load().dbmp_set_schedule(ctx, int(schedule), int(workgroups_per_cu)))
 
 
 def dbmp_set_atlas(ctx, stream, atlas, B, Hb, Wb, atlas_dtype):

@@ -264,6 +264,53 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
 // ------------------------------------------------------------------------------------------
 // Host launcher
 // ------------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------------
+// k_order: tiles by decreasing list length, for the sorted and persistent schedules. One
+// workgroup: a histogram of the lengths (capped at ORDER_BINS - 1) in LDS, an exclusive scan of
+// the bins from the longest down, then a scatter. Ties are placed in any order: every tile is
+// computed independently, so the order changes no image bit.
+// ------------------------------------------------------------------------------------------
+constexpr int ORDER_BINS = 1024;
+
+__global__ void __launch_bounds__(ORDER_BINS)
+k_order(const int *__restrict__ tile_count, int n_tiles, int *__restrict__ order)
+{
+    __shared__ int hist[ORDER_BINS];
+    __shared__ int wsum[ORDER_BINS / 64];
+    const int t = threadIdx.x;
+    hist[t] = 0;
+    __syncthreads();
+    // bin 0 holds the longest lists
+    auto bin = [](int len) { return ORDER_BINS - 1 - min(max(len, 0), ORDER_BINS - 1); };
+    for (int i = t; i < n_tiles; i += ORDER_BINS) atomicAdd(&hist[bin(tile_count[i])], 1);
+    __syncthreads();
+    // exclusive scan over the bins: wave-inclusive scans, then the wave totals
+    const int v = hist[t];
+    int x = v;
+    const int lane = t & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[t >> 6] = x;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < (t >> 6); ++w) base += wsum[w];
+    hist[t] = base + x - v;
+    __syncthreads();
+    for (int i = t; i < n_tiles; i += ORDER_BINS) {
+        const int pos = atomicAdd(&hist[bin(tile_count[i])], 1);
+        order[pos] = i;
+    }
+}
+
+hipError_t launch_order(const int *tile_count, int n_tiles, int *order, hipStream_t st)
+{
+    if (n_tiles > 0) k_order<<<1, ORDER_BINS, 0, st>>>(tile_count, n_tiles, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_binning(const BinArgs &a, hipStream_t st)
 {
     if (a.pad_atlas) {

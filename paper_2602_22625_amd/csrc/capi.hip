@@ -13,6 +13,10 @@
 
 using namespace dbmp;
 
+static_assert(DBMP_SCHED_GRID == SCHED_GRID && DBMP_SCHED_SORTED == SCHED_SORTED &&
+                  DBMP_SCHED_PERSISTENT == SCHED_PERSISTENT,
+              "schedule codes of the ABI and the kernels agree");
+
 namespace {
 
 struct Buf {
@@ -26,8 +30,12 @@ struct dbmp_ctx {
     int device = 0;
     std::string err;
     Buf recs, tile_count, tile_len, lists, saveK, saveT, atlas_pad, box, imgs, flags, counter,
-        list_max, loss_tile;
+        list_max, loss_tile, order, queue;
     int list_cap = 0;  // entries per tile list
+    // launch schedule of the raster kernels (dbmp_set_schedule)
+    int sched = SCHED_GRID;
+    int wgs_per_cu = 4;
+    int n_cu = 256;
     // the padded atlas held in atlas_pad (set by dbmp_set_atlas or a render given an atlas)
     bool atlas_valid = false;
     int atlas_B = 0, atlas_Hb = 0, atlas_Wb = 0, atlas_dtype = 0;
@@ -214,6 +222,9 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     if ((rc = ensure(c, c->lists, 4 * (size_t)tiles * c->list_cap, st, "tile lists"))) return rc;
     if ((rc = ensure(c, c->saveK, 4 * (size_t)n_pix, st, "saveK"))) return rc;
     if ((rc = ensure(c, c->saveT, 4 * (size_t)n_pix, st, "saveT"))) return rc;
+    if (c->sched != SCHED_GRID &&
+        (rc = ensure(c, c->order, 4 * (size_t)tiles, st, "tile order")))
+        return rc;
     if (c->imgs.cap < sizeof(ImgDev) * ni || !same_imgs(imgs, c->imgs_uploaded)) {
         if (capturing(st))
             return fail(c, DBMP_ESTATE,
@@ -237,6 +248,10 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ba.list_cap = c->list_cap; ba.flags = (int *)c->flags.p; ba.pad_atlas = false;
     hipError_t e = launch_binning(ba, st);
     if (e != hipSuccess) return hip_fail(c, e, "binning launch");
+    if (c->sched != SCHED_GRID) {
+        e = launch_order((const int *)c->tile_count.p, (int)tiles, (int *)c->order.p, st);
+        if (e != hipSuccess) return hip_fail(c, e, "order launch");
+    }
 
     RasterArgs &ra = c->ra;
     ra = RasterArgs{};
@@ -254,6 +269,10 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.flags = (const int *)c->flags.p; ra.TS = tile;
     ra.pair_counter = (unsigned long long *)c->counter.p;
     ra.loss_tile = (float *)c->loss_tile.p;
+    ra.sched = c->sched;
+    ra.grid = c->n_cu * c->wgs_per_cu;
+    ra.order = (const int *)c->order.p;
+    ra.queue = (int *)c->queue.p;
     e = launch_raster_fwd(ra, st);
     if (e != hipSuccess) {
         // the appended counts were not consumed: clear them for the next forward
@@ -286,8 +305,14 @@ int dbmp_create(dbmp_ctx **out, int device, long long list_capacity)
     int rc = ensure(c, c->flags, 4 * F_COUNT, nullptr, "flags");
     if (!rc) rc = ensure(c, c->counter, 8 * DBMP_COUNTER_SLOTS, nullptr, "counter");
     if (!rc) rc = ensure(c, c->list_max, 4 * DBMP_COUNTER_SLOTS, nullptr, "list_max");
+    if (!rc) rc = ensure(c, c->queue, 16, nullptr, "work queues");
     if (rc) { dbmp_destroy(c); return rc; }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) ==
+            hipSuccess && ncu > 0)
+        c->n_cu = ncu;
     hipError_t e = hipMemset(c->flags.p, 0, 4 * F_COUNT);
+    if (e == hipSuccess) e = hipMemset(c->queue.p, 0, 16);
     if (e == hipSuccess) e = hipMemset(c->counter.p, 0, 8 * DBMP_COUNTER_SLOTS);
     if (e == hipSuccess) e = hipMemset(c->list_max.p, 0, 4 * DBMP_COUNTER_SLOTS);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -304,7 +329,7 @@ int dbmp_destroy(dbmp_ctx *c)
         (void)hipDeviceSynchronize();
         Buf *bs[] = {&c->recs, &c->tile_count, &c->tile_len, &c->lists, &c->saveK, &c->saveT,
                      &c->atlas_pad, &c->box, &c->imgs, &c->flags, &c->counter, &c->list_max,
-                     &c->loss_tile};
+                     &c->loss_tile, &c->order, &c->queue};
         for (Buf *b : bs)
             if (b->p) (void)hipFree(b->p);
     }
@@ -325,6 +350,19 @@ int dbmp_reserve(dbmp_ctx *c, long long list_capacity)
     e = hipMemset(c->list_max.p, 0, 4 * DBMP_COUNTER_SLOTS);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "statistics reset");
+    return DBMP_OK;
+}
+
+int dbmp_set_schedule(dbmp_ctx *c, int schedule, int workgroups_per_cu)
+{
+    if (!c) return DBMP_EINVAL;
+    if (schedule != DBMP_SCHED_GRID && schedule != DBMP_SCHED_SORTED &&
+        schedule != DBMP_SCHED_PERSISTENT)
+        return fail(c, DBMP_EINVAL, "unknown schedule");
+    if (workgroups_per_cu < 1 || workgroups_per_cu > 32)
+        return fail(c, DBMP_EINVAL, "workgroups_per_cu must be in [1, 32]");
+    c->sched = schedule;
+    c->wgs_per_cu = workgroups_per_cu;
     return DBMP_OK;
 }
 

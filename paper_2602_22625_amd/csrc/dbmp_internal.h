@@ -142,9 +142,22 @@ struct RasterArgs {
     unsigned long long *pair_counter;  // cumulative count of evaluated (pixel, primitive) pairs
     const float *target;               // non-NULL: the backward forms the MSE gradient itself
     float *loss_tile;                  // per-tile sums of squared errors (MSE backward)
+    int sched;                         // SCHED_GRID, SCHED_SORTED or SCHED_PERSISTENT
+    int grid;                          // workgroups of a persistent launch
+    const int *order;                  // tiles by decreasing list length (SORTED, PERSISTENT)
+    int *queue;                        // persistent work queues: fwd {head, done}, bwd {head, done}
 };
 
+// How the raster kernels map workgroups to tiles.
+//   SCHED_GRID        one workgroup per tile, tiles in XCD-banded image order;
+//   SCHED_SORTED      one workgroup per tile, tiles dealt longest list first;
+//   SCHED_PERSISTENT  a fixed number of workgroups take tiles, longest list first, from a
+//                     device queue until it is empty.
+enum { SCHED_GRID = 0, SCHED_SORTED = 1, SCHED_PERSISTENT = 2 };
+
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);
+// order[0 .. n_tiles): tiles by decreasing list length (counting sort of tile_count).
+hipError_t launch_order(const int *tile_count, int n_tiles, int *order, hipStream_t st);
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_loss_sum(const float *loss_tile, const ImgDev *imgs, int n_images, float *out,

@@ -35,6 +35,8 @@
 
 #include <limits.h>
 
+#include <algorithm>
+
 namespace dbmp {
 
 template <int TS>
@@ -154,6 +156,37 @@ __device__ __forceinline__ void bitonic_sort(int n, Get get, Set set, Sync sync)
     }
 }
 
+// Runs `body(tile)` for the tiles this workgroup owns under the launch schedule (see SCHED_*).
+// Persistent: thread 0 takes the next item from the queue and shares it through LDS; the
+// barrier at the top of each round also guarantees every lane has finished the previous tile
+// before its LDS is reused. The last workgroup to leave re-arms the queue for the next launch.
+template <typename Body>
+__device__ __forceinline__ void run_schedule(int sched, const int *__restrict__ order,
+                                             int *__restrict__ queue, int n_tiles, Body body)
+{
+    if (sched != SCHED_PERSISTENT) {
+        body(sched == SCHED_SORTED ? order[blockIdx.x] : xcd_remap(blockIdx.x, n_tiles));
+        return;
+    }
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= n_tiles) break;  // every workgroup reaches this once the queue is drained
+        body(order[item]);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+            queue[0] = 0;
+            queue[1] = 0;
+            __threadfence();
+        }
+    }
+}
+
 template <int TS, typename TexT, bool BG_PP>
 __global__ void __launch_bounds__(TS * TS)
 k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
@@ -162,86 +195,87 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
              const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
              float *__restrict__ saveT, const int *__restrict__ flags,
-             unsigned long long *__restrict__ pair_counter)
+             unsigned long long *__restrict__ pair_counter, int sched,
+             const int *__restrict__ order, int *__restrict__ queue)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
     __shared__ __attribute__((aligned(16))) int s_ids[CAP + 4];
-    const int tile = xcd_remap(blockIdx.x, n_tiles);
-    const int n = tile_count[tile];
-    __syncthreads();  // every lane has read the count before it is re-armed
-    if (threadIdx.x == 0) {
-        tile_count[tile] = 0;  // ready for the next forward's appends
-        tile_len[tile] = n;    // for the backward
-        atomicMax(list_max + (blockIdx.x & (DBMP_COUNTER_SLOTS - 1)), n);  // statistic
-    }
-    if (n > list_cap) return;  // this tile's list did not fit (reported by dbmp_check)
-    const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
-    int *seg = lists + (size_t)tile * list_cap;
-    const bool in_lds = n <= CAP;
-
-    // ---- sort the tile's list front to back (index order) and write it back -----------------
-    if (in_lds) {
-        for (int i = threadIdx.x; i < n + 4; i += NT) s_ids[i] = i < n ? seg[i] : INT_MAX;
-        __syncthreads();
-        if (n <= NT) {  // rank sort: entries are distinct primitive ids
-            int v = INT_MAX, rank = 0;
-            if ((int)threadIdx.x < n) {
-                v = s_ids[threadIdx.x];
-                for (int k = 0; k < n; k += 4) {
-                    const int4 q = *reinterpret_cast<const int4 *>(&s_ids[k]);
-                    rank += (q.x < v) + (q.y < v) + (q.z < v) + (q.w < v);
-                }
-            }
-            __syncthreads();
-            if ((int)threadIdx.x < n) s_ids[rank] = v;
-        } else {
-            bitonic_sort<NT>(n, [&](int i) { return s_ids[i]; },
-                             [&](int i, int x) { s_ids[i] = x; }, [] { __syncthreads(); });
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += NT) seg[i] = s_ids[i];
-    } else {  // longer than the LDS buffer: sort in place in global memory
-        volatile int *vs = seg;
-        bitonic_sort<NT>(n, [&](int i) { return vs[i]; }, [&](int i, int x) { vs[i] = x; },
-                         [] { __threadfence_block(); __syncthreads(); });
-    }
-
-    // ---- composite ------------------------------------------------------------------------
-    const double xd = tg.px, yd = tg.py;
-    const uint64_t vmask = __ballot(tg.valid);
-    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, TK = 1.f;
-    int K = -1;
-    unsigned long long npairs = 0;  // wave-uniform count of evaluated (pixel, primitive) pairs
     __shared__ PrimRec s_rec[BATCH];
-    auto composite = [&](auto id_at) {
-        for (int b0 = 0; b0 < n; b0 += BATCH) {
-            const int cnt = min(BATCH, n - b0);
-            __syncthreads();  // the previous batch is consumed (first pass: the sort is done)
-            stage_batch<NT>(s_rec, recs, b0, cnt, id_at);
+    auto tile_body = [&](const int tile) {
+        const int n = tile_count[tile];
+        __syncthreads();  // every lane has read the count before it is re-armed
+        if (threadIdx.x == 0) {
+            tile_count[tile] = 0;  // ready for the next forward's appends
+            tile_len[tile] = n;    // for the backward
+            atomicMax(list_max + (blockIdx.x & (DBMP_COUNTER_SLOTS - 1)), n);  // statistic
+        }
+        if (n > list_cap) return;  // this tile's list did not fit (reported by dbmp_check)
+        const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
+        int *seg = lists + (size_t)tile * list_cap;
+        const bool in_lds = n <= CAP;
+
+        // ---- sort the tile's list front to back (index order) and write it back -----------------
+        if (in_lds) {
+            for (int i = threadIdx.x; i < n + 4; i += NT) s_ids[i] = i < n ? seg[i] : INT_MAX;
             __syncthreads();
-            uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
-            while (hits) {  // ascending list order: front to back
-                const int e = __builtin_ctzll(hits);
-                hits &= hits - 1;
-                const PrimRec &r = s_rec[e];
-                const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-                const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-                const uint64_t m = support_mask(r, U, V, vmask);
-                if (m == 0) continue;  // no lane of this wave touches the primitive
-                npairs += __popcll(m);
-                if (__builtin_amdgcn_inverse_ballot_w64(m)) {
-                    float M, MU, MV;
-                    bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
-                    const float a = r.ka * M;  // Eq. (3)
-                    if (T >= DBMP_TAU) { K = b0 + e; TK = T; }
-                    const float w = T * a;
-                    C0 = fmaf(w, r.cr, C0);
-                    C1 = fmaf(w, r.cg, C1);
-                    C2 = fmaf(w, r.cb, C2);
-                    T = T * (1.f - a);
+            if (n <= NT) {  // rank sort: entries are distinct primitive ids
+                int v = INT_MAX, rank = 0;
+                if ((int)threadIdx.x < n) {
+                    v = s_ids[threadIdx.x];
+                    for (int k = 0; k < n; k += 4) {
+                        const int4 q = *reinterpret_cast<const int4 *>(&s_ids[k]);
+                        rank += (q.x < v) + (q.y < v) + (q.z < v) + (q.w < v);
+                    }
+                }
+                __syncthreads();
+                if ((int)threadIdx.x < n) s_ids[rank] = v;
+            } else {
+                bitonic_sort<NT>(n, [&](int i) { return s_ids[i]; },
+                                 [&](int i, int x) { s_ids[i] = x; }, [] { __syncthreads(); });
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += NT) seg[i] = s_ids[i];
+        } else {  // longer than the LDS buffer: sort in place in global memory
+            volatile int *vs = seg;
+            bitonic_sort<NT>(n, [&](int i) { return vs[i]; }, [&](int i, int x) { vs[i] = x; },
+                             [] { __threadfence_block(); __syncthreads(); });
+        }
+
+        // ---- composite ------------------------------------------------------------------------
+        const double xd = tg.px, yd = tg.py;
+        const uint64_t vmask = __ballot(tg.valid);
+        float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, TK = 1.f;
+        int K = -1;
+        unsigned long long npairs = 0;  // wave-uniform count of evaluated (pixel, primitive) pairs
+        auto composite = [&](auto id_at) {
+            for (int b0 = 0; b0 < n; b0 += BATCH) {
+                const int cnt = min(BATCH, n - b0);
+                __syncthreads();  // the previous batch is consumed (first pass: the sort is done)
+                stage_batch<NT>(s_rec, recs, b0, cnt, id_at);
+                __syncthreads();
+                uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
+                while (hits) {  // ascending list order: front to back
+                    const int e = __builtin_ctzll(hits);
+                    hits &= hits - 1;
+                    const PrimRec &r = s_rec[e];
+                    const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+                    const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+                    const uint64_t m = support_mask(r, U, V, vmask);
+                    if (m == 0) continue;  // no lane of this wave touches the primitive
+                    npairs += __popcll(m);
+                    if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+                        float M, MU, MV;
+                        bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
+                        const float a = r.ka * M;  // Eq. (3)
+                        if (T >= DBMP_TAU) { K = b0 + e; TK = T; }
+                        const float w = T * a;
+                        C0 = fmaf(w, r.cr, C0);
+                        C1 = fmaf(w, r.cg, C1);
+                        C2 = fmaf(w, r.cb, C2);
+                        T = T * (1.f - a);
+                    }
                 }
             }
-        }
     };
     if (in_lds)
         composite([&](int j) { return s_ids[j]; });
@@ -269,6 +303,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
     if (alpha) alpha[gp] = 1.f - T;
     saveK[gp] = K;
     saveT[gp] = TK;
+    };
+    run_schedule(sched, order, queue, n_tiles, tile_body);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -337,110 +373,113 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
              const float *__restrict__ gI, const float *__restrict__ target,
              float *__restrict__ loss_tile, const float *__restrict__ gA,
              float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
-             const int *__restrict__ flags)
+             const int *__restrict__ flags, int sched, const int *__restrict__ order,
+             int *__restrict__ queue)
 {
-    const int tile = xcd_remap(blockIdx.x, n_tiles);
-    const int n = tile_len[tile];
-    if (n > list_cap) return;  // the forward did not render this tile
-    const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
-    const int lane = threadIdx.x & 63;
-    const ImgDev &D = tg.D;
-    const double xd = tg.px, yd = tg.py;
-    const uint64_t vmask = __ballot(tg.valid);
-    const size_t plane = (size_t)D.H * D.W;
-    const long long gp = D.pix_off + tg.pix;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, ga = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, TK = 0.f;
-    float sq = 0.f;
-    int K = -1;
-    if (tg.valid) {
-        const float *gp3 = gI + 3 * D.pix_off + tg.pix;  // MSE: the forward's image
-        g0 = gp3[0]; g1 = gp3[plane]; g2 = gp3[2 * plane];
-        if (MSE) {
-            const float *tp = target + 3 * D.pix_off + tg.pix;
-            const float e0 = g0 - tp[0], e1 = g1 - tp[plane], e2 = g2 - tp[2 * plane];
-            sq = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
-            const float sc = 2.f / (3.f * (float)plane);  // mean over the image's 3HW values
-            g0 = sc * e0; g1 = sc * e1; g2 = sc * e2;
-        }
-        if (HAS_GA) ga = gA[gp];
-        if (BG_PP) {
-            const float *bp = bg + 3 * D.pix_off + tg.pix;
-            G0 = bp[0]; G1 = bp[plane]; G2 = bp[2 * plane];
-        } else {
-            G0 = bg[3 * tg.b]; G1 = bg[3 * tg.b + 1]; G2 = bg[3 * tg.b + 2];
-        }
-        K = saveK[gp];
-        TK = saveT[gp];
-    }
-    float Bk = 1.f, Trun = TK;
-    const int *seg = lists + (size_t)tile * list_cap;
     __shared__ PrimRec s_rec[BATCH];
-    for (int hi = n; hi > 0; hi -= BATCH) {
-        const int b0 = max(0, hi - BATCH), cnt = hi - b0;
-        __syncthreads();  // the previous batch is consumed
-        stage_batch<TS * TS>(s_rec, recs, b0, cnt, [&](int j) { return seg[j]; });
-        __syncthreads();
-        uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
-        while (hits) {  // descending list order: back to front
-            const int e = 63 - __builtin_clzll(hits);
-            hits ^= 1ull << e;
-            const PrimRec &r = s_rec[e];
-            const int j = b0 + e;
-            const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-            const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-            const uint64_t msk = support_mask(r, U, V, vmask);
-            if (msk == 0) continue;
-            float d[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) d[q] = 0.f;
-            if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
-                float M, MU, MV;
-                bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
-                const float a = r.ka * M;
-                const float m = 1.f - a;
-                // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
-                float rc = __builtin_amdgcn_rcpf(m);
-                rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
-                const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
-                Trun = Tj;
-                const float cr = r.cr, cg = r.cg, cb = r.cb;
-                float dal = g0 * (cr - G0);
-                dal = fmaf(g1, cg - G1, dal);
-                dal = fmaf(g2, cb - G2, dal);
-                if (HAS_GA) dal = fmaf(ga, Bk, dal);
-                dal *= Tj;
-                const float ta = Tj * a;
-                d[5] = g0 * ta * r.ccr;
-                d[6] = g1 * ta * r.ccg;
-                d[7] = g2 * ta * r.ccb;
-                d[4] = dal * r.kaom * M;
-                const float dM = dal * r.ka;
-                const float gU = dM * MU, gV = dM * MV;
-                const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
-                d[0] = -fmaf(gU, r.faU, gV * r.faV);
-                d[1] = -fmaf(gU, r.fbU, gV * r.fbV);
-                d[2] = -fmaf(gU, Ub, gV * Vb);
-                d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
-                G0 = fmaf(m, G0, a * cr);
-                G1 = fmaf(m, G1, a * cg);
-                G2 = fmaf(m, G2, a * cb);
-                Bk *= m;
+    __shared__ float s_loss[TS * TS / 64];
+    auto tile_body = [&](const int tile) {
+        const int n = tile_len[tile];
+        if (n > list_cap) return;  // the forward did not render this tile
+        const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
+        const int lane = threadIdx.x & 63;
+        const ImgDev &D = tg.D;
+        const double xd = tg.px, yd = tg.py;
+        const uint64_t vmask = __ballot(tg.valid);
+        const size_t plane = (size_t)D.H * D.W;
+        const long long gp = D.pix_off + tg.pix;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, ga = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f, TK = 0.f;
+        float sq = 0.f;
+        int K = -1;
+        if (tg.valid) {
+            const float *gp3 = gI + 3 * D.pix_off + tg.pix;  // MSE: the forward's image
+            g0 = gp3[0]; g1 = gp3[plane]; g2 = gp3[2 * plane];
+            if (MSE) {
+                const float *tp = target + 3 * D.pix_off + tg.pix;
+                const float e0 = g0 - tp[0], e1 = g1 - tp[plane], e2 = g2 - tp[2 * plane];
+                sq = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+                const float sc = 2.f / (3.f * (float)plane);  // mean over the image's 3HW values
+                g0 = sc * e0; g1 = sc * e1; g2 = sc * e2;
             }
-            const float tot = reduce8(d, lane);
-            if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
+            if (HAS_GA) ga = gA[gp];
+            if (BG_PP) {
+                const float *bp = bg + 3 * D.pix_off + tg.pix;
+                G0 = bp[0]; G1 = bp[plane]; G2 = bp[2 * plane];
+            } else {
+                G0 = bg[3 * tg.b]; G1 = bg[3 * tg.b + 1]; G2 = bg[3 * tg.b + 2];
+            }
+            K = saveK[gp];
+            TK = saveT[gp];
         }
-    }
-    if (MSE) {
-        __shared__ float s_loss[TS * TS / 64];
-        const float ws = wave_sum(sq);
-        if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float t = 0.f;
-            for (int w = 0; w < TS * TS / 64; ++w) t += s_loss[w];
-            loss_tile[tile] = t;
+        float Bk = 1.f, Trun = TK;
+        const int *seg = lists + (size_t)tile * list_cap;
+        for (int hi = n; hi > 0; hi -= BATCH) {
+            const int b0 = max(0, hi - BATCH), cnt = hi - b0;
+            __syncthreads();  // the previous batch is consumed
+            stage_batch<TS * TS>(s_rec, recs, b0, cnt, [&](int j) { return seg[j]; });
+            __syncthreads();
+            uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
+            while (hits) {  // descending list order: back to front
+                const int e = 63 - __builtin_clzll(hits);
+                hits ^= 1ull << e;
+                const PrimRec &r = s_rec[e];
+                const int j = b0 + e;
+                const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+                const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+                const uint64_t msk = support_mask(r, U, V, vmask);
+                if (msk == 0) continue;
+                float d[8];
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) d[q] = 0.f;
+                if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
+                    float M, MU, MV;
+                    bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
+                    const float a = r.ka * M;
+                    const float m = 1.f - a;
+                    // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
+                    float rc = __builtin_amdgcn_rcpf(m);
+                    rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
+                    const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
+                    Trun = Tj;
+                    const float cr = r.cr, cg = r.cg, cb = r.cb;
+                    float dal = g0 * (cr - G0);
+                    dal = fmaf(g1, cg - G1, dal);
+                    dal = fmaf(g2, cb - G2, dal);
+                    if (HAS_GA) dal = fmaf(ga, Bk, dal);
+                    dal *= Tj;
+                    const float ta = Tj * a;
+                    d[5] = g0 * ta * r.ccr;
+                    d[6] = g1 * ta * r.ccg;
+                    d[7] = g2 * ta * r.ccb;
+                    d[4] = dal * r.kaom * M;
+                    const float dM = dal * r.ka;
+                    const float gU = dM * MU, gV = dM * MV;
+                    const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
+                    d[0] = -fmaf(gU, r.faU, gV * r.faV);
+                    d[1] = -fmaf(gU, r.fbU, gV * r.fbV);
+                    d[2] = -fmaf(gU, Ub, gV * Vb);
+                    d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
+                    G0 = fmaf(m, G0, a * cr);
+                    G1 = fmaf(m, G1, a * cg);
+                    G2 = fmaf(m, G2, a * cb);
+                    Bk *= m;
+                }
+                const float tot = reduce8(d, lane);
+                if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
+            }
         }
-    }
+        if (MSE) {
+            const float ws = wave_sum(sq);
+            if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                float t = 0.f;
+                for (int w = 0; w < TS * TS / 64; ++w) t += s_loss[w];
+                loss_tile[tile] = t;
+            }
+        }
+    };
+    run_schedule(sched, order, queue, n_tiles, tile_body);
 }
 
 __global__ void k_fill0(float *__restrict__ p, long long n)
@@ -474,22 +513,24 @@ __global__ void __launch_bounds__(256) k_loss_sum(const float *__restrict__ lt,
 template <int TS, typename TexT, bool BGPP>
 static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
-    k_raster_fwd<TS, TexT, BGPP><<<a.n_tiles, TS * TS, 0, st>>>(
+    const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
+    k_raster_fwd<TS, TexT, BGPP><<<grid, TS * TS, 0, st>>>(
         a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len, a.list_max,
         a.imgs,
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
-        a.saveT, a.flags, a.pair_counter);
+        a.saveT, a.flags, a.pair_counter, a.sched, a.order, a.queue);
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA, bool MSE>
 static void bwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
-    k_raster_bwd<TS, TexT, BGPP, GA, MSE><<<a.n_tiles, TS * TS, 0, st>>>(
+    const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
+    k_raster_bwd<TS, TexT, BGPP, GA, MSE><<<grid, TS * TS, 0, st>>>(
         a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
         (const TexT *)a.atlas_pad, a.Wp, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI, a.target,
         a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
-        (float)(cv / cu), a.flags);
+        (float)(cv / cu), a.flags, a.sched, a.order, a.queue + 2);
 }
 
 template <int TS, typename TexT>

@@ -44,10 +44,13 @@ class Fitter:
     # One Adam iteration, enqueued on the current stream: forward (the atlas was stored once),
     # backward with the MSE gradient formed inside the kernel and accumulated into a gradient
     # buffer that Adam zeroes after reading: four kernels per step.
-    def _enqueue(self):
-        st = capi.stream_handle()
+    def _render(self):
         self.R.render(self.params, self.atlas_idx, None, self.H, self.W, self.bg,
                       self.alpha_max, self.tile, image=self.image, with_alpha=False)
+
+    def _enqueue(self):
+        st = capi.stream_handle()
+        self._render()
         self.R.backward_mse(self.target, None, out=self.grad, accumulate=self.accumulate)
         capi.dbmp_adam_step(st, self.params, self.grad, self.m, self.v, self.params.numel(),
                             self.lr, self.betas[0], self.betas[1], self.eps, self.step_count,
@@ -56,8 +59,7 @@ class Fitter:
     def _size(self):
         """Store the atlas, render once synchronously and size the tile lists with headroom."""
         self.R.set_atlas(self.atlas)
-        self.R.render(self.params, self.atlas_idx, None, self.H, self.W, self.bg,
-                      self.alpha_max, self.tile, image=self.image, with_alpha=False)
+        self._render()
         rc = capi.dbmp_check(self.R.ctx, capi.stream_handle())
         need = self.R.longest_list()
         capi.dbmp_reserve(self.R.ctx, int(need * self.headroom) + 1)
@@ -141,3 +143,101 @@ class Fitter:
     def psnr(self):
         import math
         return 10.0 * math.log10(1.0 / max(self.loss(), 1e-30))
+
+    def set_launch(self, tile, schedule, workgroups_per_cu):
+        """Tile size and launch schedule; drops a captured graph and re-sizes the lists."""
+        self.tile = tile
+        self.R.set_schedule(schedule, workgroups_per_cu)
+        self.graph = None
+        self._sized = False
+
+    def autotune(self, tuner, key, steps=3, cands=None, force=False):
+        """Choose tile size and schedule with `tuner` (an autotune.Autotuner): each candidate
+        runs `steps` timed eager steps after a sizing step; the optimiser state is restored
+        afterwards, so tuning leaves the trajectory unchanged. Returns the chosen cfg."""
+        snap = self.snapshot()
+
+        def measure(cfg):
+            self.set_launch(*cfg)
+            self.step()  # sizing and first launches, untimed
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                self.step()
+            e1.record(st)
+            self.check()
+            self.restore(snap)
+            return e0.elapsed_time(e1) * 1e-3 / steps
+
+        best = tuner.tune(key, measure, cands, force)
+        self.restore(snap)
+        self.set_launch(*best)
+        return best
+
+
+class BatchFitter(Fitter):
+    """Many independent fits advanced together: one batched forward (all images' tiles in one
+    launch per stage), one MSE backward, one Adam over all parameters, captured as one graph
+    per step. fits: list of (params [N_i, 8], atlas_idx [N_i], target [3, H_i, W_i]) on the
+    device; images share the atlas, alpha_max and the tile size. bg: [n_images, 3] or None
+    (white)."""
+
+    def __init__(self, fits, atlas, bg=None, alpha_max=1.0, tile=16, lr=1e-2,
+                 betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0):
+        dev = fits[0][0].device
+        self.descs = []
+        prim, pix = 0, 0
+        for p, _, t in fits:
+            H, W = int(t.shape[1]), int(t.shape[2])
+            self.descs.append((H, W, int(p.shape[0]), prim, pix))
+            prim += int(p.shape[0])
+            pix += H * W
+        self.n_images = len(fits)
+        self.params = torch.cat([p.detach().float() for p, _, _ in fits]).contiguous()
+        self.N = self.params.shape[0]
+        self.atlas_idx = torch.cat([i for _, i, _ in fits]).contiguous()
+        self.atlas = atlas
+        self.target = torch.cat([t.reshape(-1) for _, _, t in fits]).contiguous()
+        self.bg = bg if bg is not None else torch.ones(self.n_images, 3, device=dev)
+        self.alpha_max, self.tile = alpha_max, tile
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step_count = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.grad = torch.zeros_like(self.params)
+        self.image = torch.empty(3 * pix, device=dev, dtype=torch.float32)
+        self.loss_buf = torch.zeros(self.n_images, device=dev, dtype=torch.float32)
+        self.R = renderer if renderer is not None else Renderer(device=dev.index, check=False)
+        self.headroom = headroom
+        self.accumulate = True
+        self.graph = None
+        self._sized = False
+
+    def _render(self):
+        self.R.render_batched(self.descs, self.params, self.atlas_idx, None, self.bg,
+                              self.alpha_max, self.tile, image=self.image, with_alpha=False)
+
+    def shapes(self):
+        return [(h, w, n) for (h, w, n, _, _) in self.descs]
+
+    def losses(self):
+        """Per-image MSE of the last step's images (synchronises)."""
+        self.R.mse_loss(self.loss_buf)
+        sse = self.loss_buf.double().cpu()
+        return [float(sse[i]) / (3 * h * w) for i, (h, w, _, _, _) in enumerate(self.descs)]
+
+    def loss(self):
+        return sum(self.losses()) / self.n_images
+
+    def psnrs(self):
+        import math
+        return [10.0 * math.log10(1.0 / max(l, 1e-30)) for l in self.losses()]
+
+    def image_of(self, i):
+        h, w, _, _, po = self.descs[i]
+        return self.image[3 * po:3 * (po + h * w)].view(3, h, w)
+
+    def params_of(self, i):
+        _, _, n, pr, _ = self.descs[i]
+        return self.params[pr:pr + n]

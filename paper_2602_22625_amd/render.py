@@ -52,6 +52,11 @@ class Renderer:
                 pass
             self.ctx = None
 
+    def set_schedule(self, schedule, workgroups_per_cu=4):
+        """Launch schedule of the raster kernels (capi.DBMP_SCHED_*); results do not depend on
+        it."""
+        capi.dbmp_set_schedule(self.ctx, schedule, workgroups_per_cu)
+
     # -- atlas -------------------------------------------------------------------------------
     def set_atlas(self, atlas):
         """Pads and stores the bitmaps once; later renders may pass atlas=None."""
@@ -112,22 +117,28 @@ class Renderer:
         return image, alpha
 
     def render_batched(self, descs, params, atlas_idx, atlas, bg, alpha_max=1.0, tile=16,
-                       image=None, alpha=None):
-        """descs: list of (H, W, N, prim_offset, pixel_offset). bg: [n_images, 3]."""
+                       image=None, alpha=None, with_alpha=True):
+        """descs: list of (H, W, N, prim_offset, pixel_offset). bg: [n_images, 3]. atlas=None
+        renders with the stored atlas."""
         _need(params, "params", torch.float32)
         _need(atlas_idx, "atlas_idx", torch.int32)
-        _need(atlas, "atlas")
         _need(bg, "bg", torch.float32, (len(descs), 3))
-        B, Hb, Wb = atlas.shape
+        if atlas is None:
+            B = Hb = Wb = 0
+            dcode = 0
+        else:
+            _need(atlas, "atlas")
+            B, Hb, Wb = atlas.shape
+            dcode = _dtype_code(atlas)
         npix = max(int(d[4]) + int(d[0]) * int(d[1]) for d in descs)
         if image is None:
             image = torch.empty(3 * npix, device=params.device, dtype=torch.float32)
-        if alpha is None:
+        if alpha is None and with_alpha:
             alpha = torch.empty(npix, device=params.device, dtype=torch.float32)
         cd = [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))
               for (h, w, n, po, xo) in descs]
         st = capi.stream_handle()
-        args = (self.ctx, st, cd, params, atlas_idx, atlas, B, Hb, Wb, _dtype_code(atlas), bg,
+        args = (self.ctx, st, cd, params, atlas_idx, atlas, B, Hb, Wb, dcode, bg,
                 alpha_max, tile, image, alpha)
         capi.dbmp_render_batched(*args)
         if self.check_each:

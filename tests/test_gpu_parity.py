@@ -304,7 +304,13 @@ def test_list_overflow_is_reported_then_grown():
     assert torch.equal(img, img2)
 
 
-def test_batched_equals_single(R):
+SCHEDULES = [(0, 4), (1, 4), (2, 1), (2, 8)]  # (schedule, workgroups per CU)
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_batched_equals_single(R, sched):
+    """Every image of a batch (uneven sizes, an empty image, gaps between primitive ranges) is
+    bitwise the single-image render, under every launch schedule."""
     from paper_2602_22625_amd.render import Renderer
     g = np.random.default_rng(12)
     atlas = synth.make_atlas("ss64x16")
@@ -322,6 +328,7 @@ def test_batched_equals_single(R):
     A = torch.tensor(atlas, device="cuda")
     bgs = torch.tensor(g.uniform(0, 1, (len(sizes), 3)).astype(np.float32), device="cuda")
     Rb = Renderer()
+    Rb.set_schedule(*sched)
     img, alp = Rb.render_batched(descs, P, I, A, bgs, 1.0, 16)
     torch.cuda.synchronize()
     for k, (H, W, N, p0, x0) in enumerate(descs):
@@ -331,6 +338,49 @@ def test_batched_equals_single(R):
         bi = img[3 * x0:3 * x0 + 3 * H * W].view(3, H, W)
         assert torch.equal(bi, si), k
         assert torch.equal(alp[x0:x0 + H * W].view(H, W), sa), k
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("tile", [8, 32])
+def test_batched_mse_backward_matches_oracle(sched, tile):
+    """Batched forward + MSE backward (each image's loss a mean over its own 3HW values) against
+    the oracle image by image, under every launch schedule; per-image losses from
+    dbmp_mse_loss."""
+    from paper_2602_22625_amd.render import Renderer
+    atlas = synth.make_atlas("ss64x16")
+    sizes = [(72, 56, 120), (40, 104, 60), (16, 16, 0), (88, 64, 200)]
+    descs, ps, ids, tg, po, xo = [], [], [], [], 0, 0
+    for k, (H, W, N) in enumerate(sizes):
+        pr, ix = synth.init_params(N, H, W, math.log(9.0), 0.5, 16, 700 + k)
+        descs.append((H, W, N, po, xo))
+        ps.append(pr); ids.append(ix)
+        tg.append(synth.target_image(H, W, 4, 800 + k).reshape(-1))
+        po += N
+        xo += H * W
+    P = torch.tensor(np.concatenate(ps), device="cuda")
+    I = torch.tensor(np.concatenate(ids), device="cuda")
+    A = torch.tensor(atlas, device="cuda")
+    T = torch.tensor(np.concatenate(tg), device="cuda")
+    bgs = torch.ones(len(sizes), 3, device="cuda")
+    Rb = Renderer()
+    Rb.set_schedule(*sched)
+    img, _ = Rb.render_batched(descs, P, I, A, bgs, 1.0, tile)
+    out = Rb.backward_mse(T, None, n_params=po)
+    loss = torch.zeros(len(sizes), device="cuda")
+    Rb.mse_loss(loss)
+    Rb.check()
+    out = out.cpu().numpy()
+    loss = loss.cpu().numpy()
+    for k, (H, W, N, p0, x0) in enumerate(descs):
+        if N == 0:
+            continue
+        ref, _ = oracle.render(ps[k], ids[k], atlas, H, W)
+        t = tg[k].reshape(3, H, W)
+        sse = float(np.sum((ref - t) ** 2))
+        assert abs(loss[k] - sse) <= 1e-5 * sse, (k, loss[k], sse)
+        _, gI = oracle.mse(ref, t)
+        gref = oracle.render_backward(ps[k], ids[k], atlas, H, W, gI)
+        assert_grads(out[p0:p0 + N], gref)
 
 
 def test_autograd_function_matches_oracle(R):
