@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=320)
     ap.add_argument("--profile", choices=["c0", "c1", "c2", "c4"], default=None,
                     help="profiling driver: only forward+backward of this workload, --steps "
@@ -79,8 +80,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2602_22625_amd import capi, metrics, synth
-    from paper_2602_22625_amd.fit import Fitter
+    from paper_2602_22625_amd import autotune, capi, metrics, synth
+    from paper_2602_22625_amd.fit import BatchFitter, Fitter
     from paper_2602_22625_amd.render import Renderer
 
     capi.load()
@@ -148,6 +149,21 @@ def main():
                             fit.params.numel(), 1e-2, 0.9, 0.999, 1e-8, fit.step_count,
                             zero_grad=1)
 
+    def kernel_time(stage, fn):
+        """Average duration of the raster kernel of `stage` (0 forward, 1 backward) itself: the
+        device records a pair of HIP events at the start and the end of each launch."""
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(reps)]
+        for e0, e1 in pairs:  # creates the events
+            e0.record(st)
+            e1.record(st)
+        fn()
+        for e0, e1 in pairs:
+            capi.dbmp_time_next_launch(R.ctx, stage, e0.cuda_event, e1.cuda_event)
+            fn()
+        torch.cuda.synchronize()
+        return float(np.mean([e0.elapsed_time(e1) for e0, e1 in pairs])) * 1e-3
+
     snap = fit.snapshot()
     capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1)
     t_fwd = timed(fwd)
@@ -155,11 +171,14 @@ def main():
     ppl = capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1) / (reps + 1)
     t_bwd = timed(bwd)
     t_adam = timed(adam)
+    k_fwd = kernel_time(0, fwd)
+    k_bwd = kernel_time(1, bwd)
     fit.restore(snap)
     bwd_flops = ppl * metrics.BWD_FLOP_PER_PAIR
-    bwd_tflops = bwd_flops / t_bwd * 1e-12
-    log("per launch: fwd(bin+raster) %.1f us, bwd(+mse) %.1f us, adam %.1f us, pairs %.0f"
-        % (t_fwd * 1e6, t_bwd * 1e6, t_adam * 1e6, ppl))
+    bwd_tflops = bwd_flops / k_bwd * 1e-12
+    log("per call: fwd(bin+raster) %.1f us, bwd(+mse) %.1f us, adam %.1f us, pairs %.0f; "
+        "kernels: k_raster_fwd %.1f us, k_raster_bwd %.1f us"
+        % (t_fwd * 1e6, t_bwd * 1e6, t_adam * 1e6, ppl, k_fwd * 1e6, k_bwd * 1e6))
     longest = R.longest_list()
     bwd_bytes = metrics.bwd_algorithmic_bytes(H, W, N, atlas.numel() * 4)
     traffic = measured_traffic("k_raster_bwd_512sq_4096prims_traffic.md")
@@ -173,18 +192,19 @@ def main():
         "frac_of_nonpacked_fp32_peak": round(bwd_tflops / 78.6, 5),
         "flop_per_pair": metrics.BWD_FLOP_PER_PAIR,
         "pairs_per_launch": round(ppl),
-        "avg_launch_us": round(t_bwd * 1e6, 2),
+        "avg_launch_us": round(k_bwd * 1e6, 2),
         "hbm_algorithmic_bytes": round(bwd_bytes),
-        "hbm_algorithmic_GBps": round(bwd_bytes / t_bwd * 1e-9, 2),
-        "hbm_frac": round(bwd_bytes / t_bwd * 1e-9 / PEAK_HBM_GBS, 5),
+        "hbm_algorithmic_GBps": round(bwd_bytes / k_bwd * 1e-9, 2),
+        "hbm_frac": round(bwd_bytes / k_bwd * 1e-9 / PEAK_HBM_GBS, 5),
         "traffic": traffic,
     }
 
     extra = {
         "adam_iters_per_s_graph": round(args.steps / wall, 2),
-        "per_launch_us": {"fwd_incl_binning": round(t_fwd * 1e6, 2),
-                          "bwd_incl_mse": round(t_bwd * 1e6, 2),
-                          "adam": round(t_adam * 1e6, 2)},
+        "per_call_us_back_to_back": {"fwd_incl_binning": round(t_fwd * 1e6, 2),
+                                     "bwd_incl_mse": round(t_bwd * 1e6, 2),
+                                     "adam": round(t_adam * 1e6, 2)},
+        "kernel_us": {"k_raster_fwd": round(k_fwd * 1e6, 2), "k_raster_bwd": round(k_bwd * 1e6, 2)},
         "fwd_plus_bwd_evals_per_s_eager": round(ppl / (t_fwd + t_bwd)),
         "psnr_after_steps": round(fit.psnr(), 3),
         "longest_tile_list": int(longest),
@@ -230,6 +250,48 @@ def main():
             "peak_mem_GB": round(torch.cuda.max_memory_allocated() / 1e9, 3)}
         log("c2: fwd %.3f ms bwd %.3f ms" % (f2 * 1e3, b2 * 1e3))
         del R2
+
+    # ---------------- 64 independent fits advanced as one batch -----------------------------------
+    if not args.no_c3:
+        import tempfile
+        atlas3, items = synth.make_batch(64, seed=3000)
+        A3 = torch.tensor(atlas3, device=dev)
+        fits = [(torch.tensor(it["params"], device=dev), torch.tensor(it["idx"], device=dev),
+                 torch.tensor(it["target"], device=dev)) for it in items]
+        bf = BatchFitter(fits, A3)
+        tuner = autotune.Autotuner(os.path.join(tempfile.gettempdir(), "dbmp_bench_tune.json"),
+                                   version=autotune.library_digest())
+        key = autotune.bucket_key(bf.shapes())
+        best = bf.autotune(tuner, key, steps=3, force=True)
+        table = tuner.entry(key)["all"]
+        bf.capture()
+        for _ in range(3):
+            bf.step()
+        bf.check()
+        capi.dbmp_support_pairs(bf.R.ctx, capi.stream_handle(), reset=1)
+        steps3 = 20
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps3):
+            bf.step()
+        torch.cuda.synchronize()
+        w3 = time.perf_counter() - t0
+        bf.check()
+        pairs3 = capi.dbmp_support_pairs(bf.R.ctx, capi.stream_handle(), reset=1)
+        grid16 = table.get("T16/grid")
+        extra["c3_64_fits"] = {
+            "fits_x_steps_per_s": round(64 * steps3 / w3, 1),
+            "ms_per_batched_step": round(1e3 * w3 / steps3, 4),
+            "evals_per_s": round(pairs3 / w3),
+            "total_pixels": int(sum(h * w for h, w, _ in bf.shapes())),
+            "total_primitives": int(bf.N),
+            "tuned": autotune.cfg_name(best),
+            "tuning_ms_per_step_eager": {k: round(v * 1e3, 4) for k, v in table.items()},
+            "speedup_vs_T16_grid_eager": round(grid16 / table[autotune.cfg_name(best)], 3)
+            if grid16 else None,
+        }
+        log("c3: %.3f ms per batched step (64 fits), tuned %s" % (1e3 * w3 / steps3, best))
+        del bf
 
     # ---------------- CPU baseline: the FP64 oracle on a window of the same workload -------------
     cpu = None

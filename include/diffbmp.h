@@ -79,14 +79,27 @@ int dbmp_reserve(dbmp_ctx *ctx, long long list_capacity);
  *   DBMP_SCHED_SORTED      one workgroup per tile, tiles dealt longest list first (a counting
  *                          sort of the tile list lengths runs after binning).
  *   DBMP_SCHED_PERSISTENT  workgroups_per_cu x (compute units) workgroups stay resident and take
- *                          tiles, longest list first, from a device work queue until it is
- *                          empty: one launch per stage however many images a batch holds.
- * workgroups_per_cu in [1, 32] (used by DBMP_SCHED_PERSISTENT). Host-only, no synchronisation;
- * the sorted schedules need a workspace that grows at the next forward (not during graph capture).
+ *                          tiles, longest list first: items_per_grab tiles at a time from a
+ *                          device work queue until it is empty, or, with items_per_grab = 0,
+ *                          every G-th tile of the order (G = the number of workgroups, no
+ *                          atomics). One launch per stage however many images a batch holds.
+ * workgroups_per_cu in [1, 32] and items_per_grab in [0, 1024] are used by
+ * DBMP_SCHED_PERSISTENT only. Host-only, no synchronisation; the sorted schedules need a
+ * workspace that grows at the next forward (not during graph capture).
  */
 typedef enum { DBMP_SCHED_GRID = 0, DBMP_SCHED_SORTED = 1, DBMP_SCHED_PERSISTENT = 2 } dbmp_schedule;
 
-int dbmp_set_schedule(dbmp_ctx *ctx, int schedule, int workgroups_per_cu);
+int dbmp_set_schedule(dbmp_ctx *ctx, int schedule, int workgroups_per_cu, int items_per_grab);
+
+/*
+ * Measurement hook: the next raster kernel launch of `stage` on this context (0: the forward
+ * compositing kernel of dbmp_render / dbmp_render_batched; 1: the backward kernel of
+ * dbmp_render_backward / dbmp_render_backward_mse) is launched so that the device records
+ * start_event when the kernel begins and stop_event when it ends (hipEvent_t handles created
+ * by the caller with timing enabled; hipEventElapsedTime then gives the kernel's own duration).
+ * One-shot; NULL, NULL disarms. Ignored for a launch made during graph capture.
+ */
+int dbmp_time_next_launch(dbmp_ctx *ctx, int stage, void *start_event, void *stop_event);
 
 /*
  * Stores the bitmap templates in the context: each bitmap is copied with a one-texel zero border

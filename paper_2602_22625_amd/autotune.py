@@ -3,7 +3,8 @@
 Candidates are tile edges T in {8, 16, 32} (one, four or sixteen 8x8-pixel waves per
 workgroup) crossed with the schedules of dbmp_set_schedule: one workgroup per tile in image
 order, one workgroup per tile longest list first, or a persistent grid of 2, 4 or 8 workgroups
-per compute unit draining a longest-first queue. Each candidate is timed over a few steps of the
+per compute unit that takes the longest-first tiles in fixed strides or from a device queue, 1
+or 16 items per grab. Each candidate is timed over a few steps of the
 caller's workload and the fastest is kept in a JSON cache keyed by a bucket of the workload's
 shape (image sizes and primitive counts) and by a digest of the built library, so a rebuilt
 kernel is tuned again.
@@ -22,15 +23,22 @@ import os
 SCHED_NAMES = {0: "grid", 1: "sorted", 2: "persistent"}
 
 
-def candidates(tiles=(8, 16, 32), persistent_wgs=(2, 4, 8)):
-    """(tile, schedule, workgroups_per_cu) triples."""
+def candidates(tiles=(8, 16, 32), persistent_wgs=(2, 4, 8), grabs=(0, 1, 16)):
+    """(tile, schedule, workgroups_per_cu, items_per_grab) tuples."""
     out = []
     for t in tiles:
-        out.append((t, 0, 4))
-        out.append((t, 1, 4))
+        out.append((t, 0, 4, 1))
+        out.append((t, 1, 4, 1))
         for w in persistent_wgs:
-            out.append((t, 2, w))
+            for g in grabs:
+                out.append((t, 2, w, g))
     return out
+
+
+def cfg_name(c):
+    if c[1] == 2:
+        return "T%d/persistent/%d/%s" % (c[0], c[2], "stride" if c[3] == 0 else "grab%d" % c[3])
+    return "T%d/%s" % (c[0], SCHED_NAMES[c[1]])
 
 
 def bucket_key(shapes):
@@ -85,10 +93,11 @@ class Autotuner:
         e = self._load().get(key)
         if e is None or e.get("version") != self.version:
             return None
-        return (e["tile"], e["schedule"], e["workgroups_per_cu"])
+        return (e["tile"], e["schedule"], e["workgroups_per_cu"], e["items_per_grab"])
 
     def tune(self, key, measure, cands=None, force=False):
-        """measure(cfg) -> seconds per step for cfg = (tile, schedule, workgroups_per_cu).
+        """measure(cfg) -> seconds per step for cfg = (tile, schedule, workgroups_per_cu,
+        items_per_grab).
         Returns the fastest cfg, from the cache unless `force` or the cache is stale."""
         if not force:
             hit = self.lookup(key)
@@ -101,8 +110,9 @@ class Autotuner:
         best = min(cands, key=lambda c: times[c])
         self._load()[key] = {
             "version": self.version, "tile": best[0], "schedule": best[1],
-            "workgroups_per_cu": best[2], "seconds_per_step": times[best],
-            "all": {"T%d/%s/%d" % (c[0], SCHED_NAMES[c[1]], c[2]): times[c] for c in cands},
+            "workgroups_per_cu": best[2], "items_per_grab": best[3],
+            "seconds_per_step": times[best],
+            "all": {cfg_name(c): times[c] for c in cands},
         }
         self._save()
         return best

@@ -51,7 +51,8 @@ def load():
         "dbmp_create": ([ctypes.POINTER(P), I, LL], I),
         "dbmp_destroy": ([P], I),
         "dbmp_reserve": ([P, LL], I),
-        "dbmp_set_schedule": ([P, I, I], I),
+        "dbmp_set_schedule": ([P, I, I, I], I),
+        "dbmp_time_next_launch": ([P, I, P, P], I),
         "dbmp_set_atlas": ([P, P, P, I, I, I, I], I),
         "dbmp_render": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P], I),
         "dbmp_render_backward": ([P, P, P, P, P], I),
@@ -112,8 +113,14 @@ def dbmp_reserve(ctx, list_capacity):
     return _chk(ctx, load().dbmp_reserve(ctx, int(list_capacity)))
 
 
-def dbmp_set_schedule(ctx, schedule, workgroups_per_cu=4):
-    return _chk(ctx, load().dbmp_set_schedule(ctx, int(schedule), int(workgroups_per_cu)))
+def dbmp_set_schedule(ctx, schedule, workgroups_per_cu=4, items_per_grab=1):
+    return _chk(ctx, load().dbmp_set_schedule(ctx, int(schedule), int(workgroups_per_cu),
+                                              int(items_per_grab)))
+
+
+def dbmp_time_next_launch(ctx, stage, start_event, stop_event):
+    """start_event / stop_event: raw hipEvent_t handles (torch.cuda.Event.cuda_event) or None."""
+    return _chk(ctx, load().dbmp_time_next_launch(ctx, int(stage), start_event, stop_event))
 
 
 def dbmp_set_atlas(ctx, stream, atlas, B, Hb, Wb, atlas_dtype):

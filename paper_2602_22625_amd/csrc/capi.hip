@@ -35,7 +35,10 @@ struct dbmp_ctx {
     // launch schedule of the raster kernels (dbmp_set_schedule)
     int sched = SCHED_GRID;
     int wgs_per_cu = 4;
+    int grab = 1;
     int n_cu = 256;
+    // one-shot timing events for the next raster launch of each stage (0 forward, 1 backward)
+    hipEvent_t time_ev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     // the padded atlas held in atlas_pad (set by dbmp_set_atlas or a render given an atlas)
     bool atlas_valid = false;
     int atlas_B = 0, atlas_Hb = 0, atlas_Wb = 0, atlas_dtype = 0;
@@ -159,6 +162,18 @@ int ensure_zeroed(dbmp_ctx *c, Buf &b, size_t bytes, hipStream_t st, const char 
     return DBMP_OK;
 }
 
+// Moves the events armed by dbmp_time_next_launch for `stage` into the launch arguments (never
+// during graph capture: the events are dropped there).
+void take_timing(dbmp_ctx *c, int stage, hipStream_t st, RasterArgs &a)
+{
+    a.ev_start = a.ev_stop = nullptr;
+    if (c->time_ev[stage][0] && !capturing(st)) {
+        a.ev_start = c->time_ev[stage][0];
+        a.ev_stop = c->time_ev[stage][1];
+    }
+    c->time_ev[stage][0] = c->time_ev[stage][1] = nullptr;
+}
+
 // Shared body of dbmp_render and dbmp_render_batched. atlas == NULL: the context's atlas.
 int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> &descs,
                 const float *params, const int32_t *atlas_idx, const void *atlas, int B, int Hb,
@@ -271,9 +286,12 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.loss_tile = (float *)c->loss_tile.p;
     ra.sched = c->sched;
     ra.grid = c->n_cu * c->wgs_per_cu;
+    ra.grab = c->grab;
     ra.order = (const int *)c->order.p;
     ra.queue = (int *)c->queue.p;
+    take_timing(c, 0, st, ra);
     e = launch_raster_fwd(ra, st);
+    ra.ev_start = ra.ev_stop = nullptr;
     if (e != hipSuccess) {
         // the appended counts were not consumed: clear them for the next forward
         (void)hipStreamSynchronize(st);
@@ -353,7 +371,18 @@ int dbmp_reserve(dbmp_ctx *c, long long list_capacity)
     return DBMP_OK;
 }
 
-int dbmp_set_schedule(dbmp_ctx *c, int schedule, int workgroups_per_cu)
+int dbmp_time_next_launch(dbmp_ctx *c, int stage, void *start_event, void *stop_event)
+{
+    if (!c) return DBMP_EINVAL;
+    if (stage != 0 && stage != 1) return fail(c, DBMP_EINVAL, "stage must be 0 or 1");
+    if (!start_event != !stop_event)
+        return fail(c, DBMP_EINVAL, "give both events or neither");
+    c->time_ev[stage][0] = (hipEvent_t)start_event;
+    c->time_ev[stage][1] = (hipEvent_t)stop_event;
+    return DBMP_OK;
+}
+
+int dbmp_set_schedule(dbmp_ctx *c, int schedule, int workgroups_per_cu, int items_per_grab)
 {
     if (!c) return DBMP_EINVAL;
     if (schedule != DBMP_SCHED_GRID && schedule != DBMP_SCHED_SORTED &&
@@ -361,8 +390,11 @@ int dbmp_set_schedule(dbmp_ctx *c, int schedule, int workgroups_per_cu)
         return fail(c, DBMP_EINVAL, "unknown schedule");
     if (workgroups_per_cu < 1 || workgroups_per_cu > 32)
         return fail(c, DBMP_EINVAL, "workgroups_per_cu must be in [1, 32]");
+    if (items_per_grab < 0 || items_per_grab > 1024)
+        return fail(c, DBMP_EINVAL, "items_per_grab must be in [0, 1024]");
     c->sched = schedule;
     c->wgs_per_cu = workgroups_per_cu;
+    c->grab = items_per_grab;
     return DBMP_OK;
 }
 
@@ -418,6 +450,7 @@ int dbmp_render_backward(dbmp_ctx *c, dbmp_stream stream, const float *dL_dimage
     a.gA = dL_dalpha;
     a.dparams = dL_dparams;
     a.n_param_floats = c->n_rows * 8;
+    take_timing(c, 1, (hipStream_t)stream, a);
     hipError_t e = launch_raster_bwd(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "backward launch");
     c->err.clear();
@@ -437,6 +470,7 @@ int dbmp_render_backward_mse(dbmp_ctx *c, dbmp_stream stream, const float *targe
     a.gA = dL_dalpha;
     a.dparams = dL_dparams;
     a.n_param_floats = accumulate ? 0 : c->n_rows * 8;  // 0: no clear before accumulating
+    take_timing(c, 1, (hipStream_t)stream, a);
     hipError_t e = launch_raster_bwd(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "backward launch");
     c->have_loss = true;

@@ -144,15 +144,17 @@ struct RasterArgs {
     float *loss_tile;                  // per-tile sums of squared errors (MSE backward)
     int sched;                         // SCHED_GRID, SCHED_SORTED or SCHED_PERSISTENT
     int grid;                          // workgroups of a persistent launch
+    int grab;                          // persistent: items per queue grab (0: static strides)
     const int *order;                  // tiles by decreasing list length (SORTED, PERSISTENT)
     int *queue;                        // persistent work queues: fwd {head, done}, bwd {head, done}
+    hipEvent_t ev_start, ev_stop;      // non-null: recorded by the device around the raster launch
 };
 
 // How the raster kernels map workgroups to tiles.
 //   SCHED_GRID        one workgroup per tile, tiles in XCD-banded image order;
 //   SCHED_SORTED      one workgroup per tile, tiles dealt longest list first;
 //   SCHED_PERSISTENT  a fixed number of workgroups take tiles, longest list first, from a
-//                     device queue until it is empty.
+//                     device queue until it is empty (or, with grab = 0, in fixed strides).
 enum { SCHED_GRID = 0, SCHED_SORTED = 1, SCHED_PERSISTENT = 2 };
 
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);

@@ -33,6 +33,8 @@
 // one float32 atomic each per (wave, primitive).
 #include "dbmp_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <limits.h>
 
 #include <algorithm>
@@ -157,25 +159,38 @@ __device__ __forceinline__ void bitonic_sort(int n, Get get, Set set, Sync sync)
 }
 
 // Runs `body(tile)` for the tiles this workgroup owns under the launch schedule (see SCHED_*).
-// Persistent: thread 0 takes the next item from the queue and shares it through LDS; the
-// barrier at the top of each round also guarantees every lane has finished the previous tile
-// before its LDS is reused. The last workgroup to leave re-arms the queue for the next launch.
+// Persistent with grab > 0: thread 0 takes the next `grab` items from the queue and shares the
+// first through LDS; the barrier at the top of each round also guarantees every lane has
+// finished the previous tile before its LDS is reused. The last workgroup to leave re-arms the
+// queue for the next launch. Persistent with grab == 0: workgroup w takes items w, w + G,
+// w + 2G, ... of the longest-first order (no atomics; the order balances the strides).
 template <typename Body>
-__device__ __forceinline__ void run_schedule(int sched, const int *__restrict__ order,
+__device__ __forceinline__ void run_schedule(int sched, int grab, const int *__restrict__ order,
                                              int *__restrict__ queue, int n_tiles, Body body)
 {
     if (sched != SCHED_PERSISTENT) {
         body(sched == SCHED_SORTED ? order[blockIdx.x] : xcd_remap(blockIdx.x, n_tiles));
         return;
     }
+    if (grab == 0) {
+        for (int item = blockIdx.x; item < n_tiles; item += gridDim.x) {
+            __syncthreads();  // the previous tile's LDS is free
+            body(order[item]);
+        }
+        return;
+    }
     __shared__ int s_item;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, grab);
         __syncthreads();
-        const int item = s_item;
-        if (item >= n_tiles) break;  // every workgroup reaches this once the queue is drained
-        body(order[item]);
+        const int first = s_item;
+        if (first >= n_tiles) break;  // every workgroup reaches this once the queue is drained
+        const int last = min(first + grab, n_tiles);
+        for (int item = first; item < last; ++item) {
+            if (item > first) __syncthreads();
+            body(order[item]);
+        }
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -195,7 +210,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
              const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
              float *__restrict__ saveT, const int *__restrict__ flags,
-             unsigned long long *__restrict__ pair_counter, int sched,
+             unsigned long long *__restrict__ pair_counter, int sched, int grab,
              const int *__restrict__ order, int *__restrict__ queue)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
@@ -304,7 +319,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
     saveK[gp] = K;
     saveT[gp] = TK;
     };
-    run_schedule(sched, order, queue, n_tiles, tile_body);
+    run_schedule(sched, grab, order, queue, n_tiles, tile_body);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -373,8 +388,8 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
              const float *__restrict__ gI, const float *__restrict__ target,
              float *__restrict__ loss_tile, const float *__restrict__ gA,
              float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
-             const int *__restrict__ flags, int sched, const int *__restrict__ order,
-             int *__restrict__ queue)
+             const int *__restrict__ flags, int sched, int grab,
+             const int *__restrict__ order, int *__restrict__ queue)
 {
     __shared__ PrimRec s_rec[BATCH];
     __shared__ float s_loss[TS * TS / 64];
@@ -479,7 +494,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             }
         }
     };
-    run_schedule(sched, order, queue, n_tiles, tile_body);
+    run_schedule(sched, grab, order, queue, n_tiles, tile_body);
 }
 
 __global__ void k_fill0(float *__restrict__ p, long long n)
@@ -510,15 +525,27 @@ __global__ void __launch_bounds__(256) k_loss_sum(const float *__restrict__ lt,
 // ------------------------------------------------------------------------------------------
 // Host launchers
 // ------------------------------------------------------------------------------------------
+// Launches `kern`; with timing events armed, through hipExtLaunchKernel, which has the device
+// record them when the kernel starts and when it ends.
+template <typename K, typename... Args>
+static void launch(K kern, int grid, int block, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                   Args... args)
+{
+    if (e0 && e1)
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, args...);
+}
+
 template <int TS, typename TexT, bool BGPP>
 static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
     const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
-    k_raster_fwd<TS, TexT, BGPP><<<grid, TS * TS, 0, st>>>(
+    launch(k_raster_fwd<TS, TexT, BGPP>, grid, TS * TS, st, a.ev_start, a.ev_stop,
         a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len, a.list_max,
         a.imgs,
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
-        a.saveT, a.flags, a.pair_counter, a.sched, a.order, a.queue);
+        a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue);
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA, bool MSE>
@@ -526,11 +553,11 @@ static void bwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
     const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
-    k_raster_bwd<TS, TexT, BGPP, GA, MSE><<<grid, TS * TS, 0, st>>>(
+    launch(k_raster_bwd<TS, TexT, BGPP, GA, MSE>, grid, TS * TS, st, a.ev_start, a.ev_stop,
         a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
         (const TexT *)a.atlas_pad, a.Wp, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI, a.target,
         a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
-        (float)(cv / cu), a.flags, a.sched, a.order, a.queue + 2);
+        (float)(cv / cu), a.flags, a.sched, a.grab, a.order, a.queue + 2);
 }
 
 template <int TS, typename TexT>

@@ -144,10 +144,10 @@ class Fitter:
         import math
         return 10.0 * math.log10(1.0 / max(self.loss(), 1e-30))
 
-    def set_launch(self, tile, schedule, workgroups_per_cu):
+    def set_launch(self, tile, schedule, workgroups_per_cu=4, items_per_grab=1):
         """Tile size and launch schedule; drops a captured graph and re-sizes the lists."""
         self.tile = tile
-        self.R.set_schedule(schedule, workgroups_per_cu)
+        self.R.set_schedule(schedule, workgroups_per_cu, items_per_grab)
         self.graph = None
         self._sized = False
 

@@ -52,10 +52,10 @@ class Renderer:
                 pass
             self.ctx = None
 
-    def set_schedule(self, schedule, workgroups_per_cu=4):
+    def set_schedule(self, schedule, workgroups_per_cu=4, items_per_grab=1):
         """Launch schedule of the raster kernels (capi.DBMP_SCHED_*); results do not depend on
         it."""
-        capi.dbmp_set_schedule(self.ctx, schedule, workgroups_per_cu)
+        capi.dbmp_set_schedule(self.ctx, schedule, workgroups_per_cu, items_per_grab)
 
     # -- atlas -------------------------------------------------------------------------------
     def set_atlas(self, atlas):

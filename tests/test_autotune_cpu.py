@@ -7,10 +7,12 @@ from paper_2602_22625_amd import autotune
 
 def test_candidates_cover_tiles_and_schedules():
     c = autotune.candidates()
-    assert {t for t, _, _ in c} == {8, 16, 32}
-    assert {s for _, s, _ in c} == {0, 1, 2}
-    assert {w for _, s, w in c if s == 2} == {2, 4, 8}
-    assert len(c) == len(set(c)) == 15
+    assert {t for t, _, _, _ in c} == {8, 16, 32}
+    assert {s for _, s, _, _ in c} == {0, 1, 2}
+    assert {w for _, s, w, _ in c if s == 2} == {2, 4, 8}
+    assert {g for _, s, _, g in c if s == 2} == {0, 1, 16}
+    assert len(c) == len(set(c)) == 33
+    assert len({autotune.cfg_name(x) for x in c}) == 33
 
 
 def test_bucket_key_rounds_sizes_and_counts():
@@ -29,28 +31,27 @@ def test_tune_picks_fastest_and_caches(tmp_path):
 
     def measure(cfg):
         calls.append(cfg)
-        t, s, w = cfg
-        return 1.0 + abs(t - 16) * 0.1 + (0.0 if s == 2 and w == 4 else 0.05)
+        t, s, w, g = cfg
+        return 1.0 + abs(t - 16) * 0.1 + (0.0 if s == 2 and w == 4 and g == 0 else 0.05)
 
     tu = autotune.Autotuner(path, version="v1")
     best = tu.tune("k", measure)
-    assert best == (16, 2, 4)
-    assert len(calls) == 15
+    assert best == (16, 2, 4, 0)
+    assert len(calls) == 33
     db = json.load(open(path))
-    assert db["k"]["tile"] == 16 and db["k"]["schedule"] == 2 and len(db["k"]["all"]) == 15
+    assert db["k"]["tile"] == 16 and db["k"]["schedule"] == 2 and len(db["k"]["all"]) == 33
     # a second tuner on the same file reuses the entry without measuring
     calls.clear()
-    assert autotune.Autotuner(path, version="v1").tune("k", measure) == (16, 2, 4)
+    assert autotune.Autotuner(path, version="v1").tune("k", measure) == (16, 2, 4, 0)
     assert calls == []
     # a different library version measures again
-    assert autotune.Autotuner(path, version="v2").tune("k", measure) == (16, 2, 4)
-    assert len(calls) == 15
+    assert autotune.Autotuner(path, version="v2").tune("k", measure) == (16, 2, 4, 0)
+    assert len(calls) == 33
 
 
 def test_tune_with_subset_and_force(tmp_path):
     path = str(tmp_path / "t.json")
     tu = autotune.Autotuner(path, version="x")
-    cands = [(8, 0, 4), (32, 1, 4)]
-    assert tu.tune("a", lambda c: {(8, 0, 4): 2.0, (32, 1, 4): 1.0}[c], cands) == (32, 1, 4)
-    assert tu.tune("a", lambda c: {(8, 0, 4): 0.5, (32, 1, 4): 1.0}[c], cands,
-                   force=True) == (8, 0, 4)
+    a, b = (8, 0, 4, 1), (32, 1, 4, 1)
+    assert tu.tune("a", lambda c: {a: 2.0, b: 1.0}[c], [a, b]) == b
+    assert tu.tune("a", lambda c: {a: 0.5, b: 1.0}[c], [a, b], force=True) == a

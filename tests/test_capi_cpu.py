@@ -47,6 +47,7 @@ def test_host_argument_checks_need_no_device():
     assert lib.dbmp_set_atlas(None, None, None, 1, 2, 2, 0) == capi.DBMP_EINVAL
     assert lib.dbmp_mse_loss(None, None, None) == capi.DBMP_EINVAL
     assert lib.dbmp_longest_list(None, None) == -1
-    assert lib.dbmp_set_schedule(None, 1, 4) == capi.DBMP_EINVAL
+    assert lib.dbmp_set_schedule(None, 1, 4, 1) == capi.DBMP_EINVAL
+    assert lib.dbmp_time_next_launch(None, 1, None, None) == capi.DBMP_EINVAL
     h = ctypes.c_void_p()
     assert lib.dbmp_create(ctypes.byref(h), 0, -5) == capi.DBMP_EINVAL

@@ -201,7 +201,7 @@ def test_batch_fitter_matches_independent_fits():
     bf.check()
 
 
-@pytest.mark.parametrize("sched", [(0, 4), (1, 4), (2, 2)])
+@pytest.mark.parametrize("sched", [(0, 4, 1), (1, 4, 1), (2, 2, 1), (2, 4, 0), (2, 8, 16)])
 def test_batch_fitter_graph_replay_matches_eager(sched):
     from paper_2602_22625_amd.fit import BatchFitter
     fits, atlas = _small_batch()
@@ -235,7 +235,7 @@ def test_batch_autotune_then_capture(tmp_path):
     fits, atlas = _small_batch()
     bf = BatchFitter(fits, atlas)
     tuner = autotune.Autotuner(str(tmp_path / "tune.json"), version="test")
-    cands = [(8, 0, 4), (16, 2, 4), (32, 1, 4)]
+    cands = [(8, 0, 4, 1), (16, 2, 4, 0), (32, 1, 4, 1)]
     key = autotune.bucket_key(bf.shapes())
     start = bf.snapshot()
     best = bf.autotune(tuner, key, steps=2, cands=cands)
@@ -247,3 +247,35 @@ def test_batch_autotune_then_capture(tmp_path):
     bf.capture()
     bf.run(10, check_every=5)
     assert all(math.isfinite(x) for x in bf.losses())
+
+
+def test_time_next_launch_records_kernel_duration():
+    """The measurement hook has the device record events around the raster kernels: durations
+    are positive, no longer than the enclosing stream interval, and the hook is one-shot."""
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c1")
+    R = Renderer(check=False)
+    p = torch.tensor(d["params"], device="cuda")
+    idx = torch.tensor(d["idx"], device="cuda")
+    a = torch.tensor(d["atlas"], device="cuda")
+    t = torch.tensor(d["target"], device="cuda")
+    R.render(p, idx, a, 512, 512, None, 1.0, 16)
+    R.backward_mse(t, None, n_params=p.shape[0])
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for e in ev:
+        e.record(st)
+    torch.cuda.synchronize()
+    ev[4].record(st)
+    capi.dbmp_time_next_launch(R.ctx, 0, ev[0].cuda_event, ev[1].cuda_event)
+    R.render(p, idx, None, 512, 512, None, 1.0, 16)
+    capi.dbmp_time_next_launch(R.ctx, 1, ev[2].cuda_event, ev[3].cuda_event)
+    out = R.backward_mse(t, None, n_params=p.shape[0])
+    R.backward_mse(t, None, out=out)  # not timed: the hook was consumed
+    ev[5].record(st)
+    torch.cuda.synchronize()
+    R.check()
+    kf, kb, wall = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5])
+    assert 0 < kf < wall and 0 < kb < wall and kf + kb < wall, (kf, kb, wall)
+    with pytest.raises(capi.DbmpError):
+        capi.dbmp_time_next_launch(R.ctx, 2, None, None)

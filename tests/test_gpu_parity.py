@@ -304,7 +304,8 @@ def test_list_overflow_is_reported_then_grown():
     assert torch.equal(img, img2)
 
 
-SCHEDULES = [(0, 4), (1, 4), (2, 1), (2, 8)]  # (schedule, workgroups per CU)
+# (schedule, workgroups per CU, items per grab)
+SCHEDULES = [(0, 4, 1), (1, 4, 1), (2, 1, 1), (2, 8, 16), (2, 4, 0)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
