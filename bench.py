@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--c4-pairs", type=int, default=10000)
+    ap.add_argument("--c4-epochs", type=int, default=10)
     ap.add_argument("--cpu-window", type=int, default=320)
     ap.add_argument("--profile", choices=["c0", "c1", "c2", "c4"], default=None,
                     help="profiling driver: only forward+backward of this workload, --steps "
@@ -292,6 +295,41 @@ def main():
         }
         log("c3: %.3f ms per batched step (64 fits), tuned %s" % (1e3 * w3 / steps3, best))
         del bf
+
+    # ---------------- learned initialiser: time to PSNR against the plain random start ---------
+    if not args.no_c4:
+        from paper_2602_22625_amd import cnn_init as ci
+        t0 = time.perf_counter()
+        tg4, fit4 = ci.generate_pairs(args.c4_pairs, steps=500, batch=256, seed=1)
+        t_data = time.perf_counter() - t0
+        log("c4: %d training pairs in %.1f s" % (args.c4_pairs, t_data))
+        net = ci.InitNet(seed=0)
+        t0 = time.perf_counter()
+        final = ci.train(net, tg4, fit4, epochs=args.c4_epochs, batch=64, lr=2e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log("c4: %d epochs in %.1f s, loss %.4f" % (args.c4_epochs, t_train, final))
+        del tg4, fit4
+        res = ci.evaluate(net, n_targets=64, plain_steps=500, learned_steps=100, seed=10 ** 6)
+        extra["c4_learned_init"] = {
+            "median_time_to_psnr_ms_learned": round(res["median_t_learned_ms"], 3),
+            "median_time_ms_plain_500_steps": round(res["median_t_plain_ms"], 3),
+            "speedup_median": round(res["median_t_plain_ms"] / res["median_t_learned_ms"], 3)
+            if math.isfinite(res["median_t_learned_ms"]) else None,
+            "wins": res["wins"], "targets": res["n"], "fallbacks": res["fallbacks"],
+            "median_cnn_inference_ms": round(res["median_t_infer_ms"], 3),
+            "median_psnr_bar_plain_500": round(res["median_psnr_bar"], 3),
+            "median_psnr_random_start": round(res["median_psnr_random_start"], 3),
+            "median_psnr_cnn_start": round(res["median_psnr_cnn_start"], 3),
+            "median_psnr_learned_after_100": round(res["median_psnr_learned_end"], 3),
+            "training_pairs": args.c4_pairs, "data_generation_s": round(t_data, 2),
+            "training_epochs": args.c4_epochs, "training_s": round(t_train, 2),
+            "training_final_loss": round(final, 5), "weights": int(net.n_params),
+        }
+        log("c4: learned %.2f ms vs plain %.2f ms (median), %d/%d wins, %d fallbacks"
+            % (res["median_t_learned_ms"], res["median_t_plain_ms"], res["wins"], res["n"],
+               res["fallbacks"]))
+        del net
 
     # ---------------- CPU baseline: the FP64 oracle on a window of the same workload -------------
     cpu = None

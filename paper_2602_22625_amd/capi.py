@@ -66,6 +66,17 @@ def load():
         "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
         "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P, I], I),
     }
+    sig.update({
+        "dbmp_cnn_conv_forward": ([P, P, I, I, I, I, P, P, I, I, P, P], I),
+        "dbmp_cnn_conv_backward_data": ([P, P, I, I, I, I, P, I, P, P], I),
+        "dbmp_cnn_conv_backward_weight": ([P, P, P, I, I, I, I, I, P, P], I),
+        "dbmp_cnn_linear_forward": ([P, P, I, I, P, P, I, I, P, P], I),
+        "dbmp_cnn_linear_backward_data": ([P, P, I, I, P, I, P, P], I),
+        "dbmp_cnn_linear_backward_weight": ([P, P, P, I, I, I, P, P], I),
+        "dbmp_cnn_cast_weights": ([P, P, I, I, I, P, P], I),
+        "dbmp_cnn_pack_input": ([P, P, I, I, I, P], I),
+        "dbmp_cnn_param_loss": ([P, P, P, P, LL, F, P, P], I),
+    })
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -186,3 +197,67 @@ def dbmp_adam_step(stream, params, grad, m, v, n, lr, beta1, beta2, eps, step, z
     return _chk(None, load().dbmp_adam_step(stream, ptr(params), ptr(grad), ptr(m), ptr(v),
                                             int(n), float(lr), float(beta1), float(beta2),
                                             float(eps), ptr(step), int(zero_grad)))
+
+
+# ------------------------------------------------------------------------------------------
+# Initialiser layers (include/dbmp_cnn.h): bf16 tensors are torch.bfloat16 (or int16 views)
+# ------------------------------------------------------------------------------------------
+HEADER_CNN = os.path.join(os.path.dirname(HERE), "include", "dbmp_cnn.h")
+
+
+def _cnn(rc, name):
+    if rc != 0:
+        raise DbmpError(rc, name)
+    return rc
+
+
+def dbmp_cnn_conv_forward(stream, x, B, H, W, Cin, w, bias, Cout, relu, y, y32=None):
+    return _cnn(load().dbmp_cnn_conv_forward(stream, ptr(x), B, H, W, Cin, ptr(w), ptr(bias),
+                                             Cout, int(relu), ptr(y), ptr(y32)),
+                "dbmp_cnn_conv_forward")
+
+
+def dbmp_cnn_conv_backward_data(stream, dz, B, H, W, Cin, wt, Cout, mask, dx):
+    return _cnn(load().dbmp_cnn_conv_backward_data(stream, ptr(dz), B, H, W, Cin, ptr(wt), Cout,
+                                                   ptr(mask), ptr(dx)),
+                "dbmp_cnn_conv_backward_data")
+
+
+def dbmp_cnn_conv_backward_weight(stream, x, dz, B, H, W, Cin, Cout, dw, db):
+    return _cnn(load().dbmp_cnn_conv_backward_weight(stream, ptr(x), ptr(dz), B, H, W, Cin, Cout,
+                                                     ptr(dw), ptr(db)),
+                "dbmp_cnn_conv_backward_weight")
+
+
+def dbmp_cnn_linear_forward(stream, x, B, K, w, bias, N, relu, y, y32=None):
+    return _cnn(load().dbmp_cnn_linear_forward(stream, ptr(x), B, K, ptr(w), ptr(bias), N,
+                                               int(relu), ptr(y), ptr(y32)),
+                "dbmp_cnn_linear_forward")
+
+
+def dbmp_cnn_linear_backward_data(stream, dz, B, N, wt, K, mask, dx):
+    return _cnn(load().dbmp_cnn_linear_backward_data(stream, ptr(dz), B, N, ptr(wt), K,
+                                                     ptr(mask), ptr(dx)),
+                "dbmp_cnn_linear_backward_data")
+
+
+def dbmp_cnn_linear_backward_weight(stream, x, dz, B, K, N, dw, db):
+    return _cnn(load().dbmp_cnn_linear_backward_weight(stream, ptr(x), ptr(dz), B, K, N,
+                                                       ptr(dw), ptr(db)),
+                "dbmp_cnn_linear_backward_weight")
+
+
+def dbmp_cnn_cast_weights(stream, w, R, T, C, wb, wt):
+    return _cnn(load().dbmp_cnn_cast_weights(stream, ptr(w), R, T, C, ptr(wb), ptr(wt)),
+                "dbmp_cnn_cast_weights")
+
+
+def dbmp_cnn_pack_input(stream, img, B, H, W, x):
+    return _cnn(load().dbmp_cnn_pack_input(stream, ptr(img), B, H, W, ptr(x)),
+                "dbmp_cnn_pack_input")
+
+
+def dbmp_cnn_param_loss(stream, pred, target, weights8, n, scale, dpred, loss):
+    return _cnn(load().dbmp_cnn_param_loss(stream, ptr(pred), ptr(target), ptr(weights8), int(n),
+                                           float(scale), ptr(dpred), ptr(loss)),
+                "dbmp_cnn_param_loss")

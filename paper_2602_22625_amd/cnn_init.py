@@ -1,0 +1,375 @@
+"""Learned initialiser: a small CNN that predicts the primitive parameters of a 256x256 target,
+trained on (target, parameters after 500 plain Adam steps) pairs that the plain fit itself
+generates, run on the library's bf16 MFMA layer kernels (include/dbmp_cnn.h).
+
+Network: six 3x3 stride-2 convolutions with ReLU (3 -> 32 -> 64 -> 128 -> 256 -> 256 -> 256
+channels, 256^2 -> 4^2 pixels), then a dense layer 4096 -> 64 with ReLU and a dense layer
+64 -> 1024 x 8 (about 2.4 M weights). float32 master weights, bf16 copies for the kernels,
+float32 accumulation; Adam on the master weights with the library's Adam kernel.
+
+Supervision (slot template): every fit starts from the same template, in which slot i (row i of
+the 1024 primitives) keeps one atlas index for all targets and starts at a uniform point of cell
+i of a 32 x 32 grid. Row i of the fitted parameters then means the same primitive across
+targets, and the network regresses them: positions as offsets from the cell centre in cell
+units, log-scale standardised, logits halved, the angle through 1 - cos(difference) (a full
+turn costs nothing). The plain random initialisation from the same template remains the
+fallback: the learned start is used only if its image error is below the random start's.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import capi, synth
+from .fit import BatchFitter, Fitter
+from .render import Renderer
+
+IMG = 256
+SLOTS = synth.SLOT_GRID * synth.SLOT_GRID
+LOG_S_MEAN, LOG_S_STD = math.log(12.0), 0.5
+CONV = [(8, 32), (32, 64), (64, 128), (128, 256), (256, 256), (256, 256)]
+FLAT = 4 * 4 * 256
+HIDDEN = 64
+OUT = SLOTS * 8
+# loss weight per parameter column: x, y, log_s, theta, nu, c_r, c_g, c_b (angles of star and
+# stroke bitmaps are ambiguous up to their symmetry: low weight)
+LOSS_W = (1.0, 1.0, 1.0, 0.1, 1.0, 1.0, 1.0, 1.0)
+CLIP = 4.0
+
+
+# ------------------------------------------------------------------------------------------
+# Parameter coding
+# ------------------------------------------------------------------------------------------
+def _cells(device):
+    i = torch.arange(SLOTS, device=device)
+    cell = IMG / synth.SLOT_GRID
+    return ((i % synth.SLOT_GRID).float() + 0.5) * cell, ((i // synth.SLOT_GRID).float() + 0.5) * cell, cell
+
+
+def encode(params):
+    """Fitted parameters [n, SLOTS, 8] -> regression targets [n, SLOTS, 8]."""
+    cx, cy, cell = _cells(params.device)
+    t = torch.empty_like(params)
+    t[..., 0] = (params[..., 0] - cx) / cell
+    t[..., 1] = (params[..., 1] - cy) / cell
+    t[..., 2] = (params[..., 2] - LOG_S_MEAN) / LOG_S_STD
+    t[..., 3] = params[..., 3]
+    t[..., 4:8] = params[..., 4:8] * 0.5
+    keep = t[..., 3].clone()
+    t = torch.clamp(t, -CLIP, CLIP)
+    t[..., 3] = keep
+    return t.contiguous()
+
+
+def decode(t):
+    cx, cy, cell = _cells(t.device)
+    p = torch.empty_like(t)
+    p[..., 0] = t[..., 0] * cell + cx
+    p[..., 1] = t[..., 1] * cell + cy
+    p[..., 2] = t[..., 2] * LOG_S_STD + LOG_S_MEAN
+    p[..., 3] = t[..., 3]
+    p[..., 4:8] = t[..., 4:8] * 2.0
+    return p
+
+
+# ------------------------------------------------------------------------------------------
+# Network
+# ------------------------------------------------------------------------------------------
+class InitNet:
+    def __init__(self, device=None, seed=0, hidden=HIDDEN):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        self.hidden = hidden
+        # (kind, R, T, C): weight [R][T][C] (+ bias [R]); conv: R = Cout, T = 9, C = Cin
+        self.layers = [("conv", co, 9, ci) for ci, co in CONV]
+        self.layers += [("fc", hidden, 1, FLAT), ("fc", OUT, 1, hidden)]
+        sizes = []
+        for _, R, T, C in self.layers:
+            sizes += [R * T * C, R]
+        self.n_params = sum(sizes)
+        self.P = torch.zeros(self.n_params, device=dev)
+        self.G = torch.zeros(self.n_params, device=dev)
+        self.m = torch.zeros(self.n_params, device=dev)
+        self.v = torch.zeros(self.n_params, device=dev)
+        self.step_count = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.w, self.b, self.gw, self.gb, self.wb, self.wt = [], [], [], [], [], []
+        off = 0
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
+        for li, (kind, R, T, C) in enumerate(self.layers):
+            n = R * T * C
+            w = self.P[off:off + n].view(R, T, C)
+            self.gw.append(self.G[off:off + n].view(R, T, C))
+            off += n
+            self.b.append(self.P[off:off + R])
+            self.gb.append(self.G[off:off + R])
+            off += R
+            fan_in = T * (3 if li == 0 else C)
+            std = math.sqrt(2.0 / fan_in) if li < len(self.layers) - 1 else 0.1 / math.sqrt(C)
+            init = torch.randn(R, T, C, generator=g) * std
+            if li == 0:
+                init[:, :, 3:] = 0.0  # padded input channels
+            w.copy_(init)
+            self.w.append(w)
+            self.wb.append(torch.empty(R, T, C, device=dev, dtype=torch.bfloat16))
+            self.wt.append(torch.empty(C, T, R, device=dev, dtype=torch.bfloat16))
+        self.w8 = torch.tensor(LOSS_W, device=dev, dtype=torch.float32)
+        self.loss_acc = torch.zeros(1, device=dev)
+        self._B = None
+        self.cast()
+
+    def cast(self):
+        st = capi.stream_handle()
+        for (kind, R, T, C), w, wb, wt in zip(self.layers, self.w, self.wb, self.wt):
+            capi.dbmp_cnn_cast_weights(st, w, R, T, C, wb, wt)
+
+    def _buffers(self, B):
+        if self._B == B:
+            return
+        dev, bf = self.device, torch.bfloat16
+        self.x0 = torch.empty(B, IMG, IMG, 8, device=dev, dtype=bf)
+        self.acts, self.dacts = [], []
+        s = IMG
+        for _, co in CONV:
+            s //= 2
+            self.acts.append(torch.empty(B, s, s, co, device=dev, dtype=bf))
+            self.dacts.append(torch.empty(B, s, s, co, device=dev, dtype=bf))
+        self.h = torch.empty(B, self.hidden, device=dev, dtype=bf)
+        self.dh = torch.empty(B, self.hidden, device=dev, dtype=bf)
+        self.out = torch.empty(B, OUT, device=dev)
+        self.dout = torch.empty(B, OUT, device=dev, dtype=bf)
+        self._B = B
+
+    def forward(self, img):
+        """img [B, 3, 256, 256] float32 (device) -> coded parameters [B, SLOTS, 8] float32."""
+        B = img.shape[0]
+        self._buffers(B)
+        st = capi.stream_handle()
+        capi.dbmp_cnn_pack_input(st, img.contiguous(), B, IMG, IMG, self.x0)
+        x, s = self.x0, IMG
+        for l, (ci, co) in enumerate(CONV):
+            capi.dbmp_cnn_conv_forward(st, x, B, s, s, ci, self.wb[l], self.b[l], co, 1,
+                                       self.acts[l], None)
+            x, s = self.acts[l], s // 2
+        L = len(CONV)
+        capi.dbmp_cnn_linear_forward(st, x, B, FLAT, self.wb[L], self.b[L], self.hidden, 1,
+                                     self.h, None)
+        capi.dbmp_cnn_linear_forward(st, self.h, B, self.hidden, self.wb[L + 1], self.b[L + 1],
+                                     OUT, 0, None, self.out)
+        return self.out.view(B, SLOTS, 8)
+
+    def backward(self):
+        """Gradients of the loss whose dL/dout (bf16) is in self.dout, ADDED into self.G."""
+        B = self._B
+        st = capi.stream_handle()
+        L = len(CONV)
+        capi.dbmp_cnn_linear_backward_weight(st, self.h, self.dout, B, self.hidden, OUT,
+                                             self.gw[L + 1], self.gb[L + 1])
+        capi.dbmp_cnn_linear_backward_data(st, self.dout, B, OUT, self.wt[L + 1], self.hidden,
+                                           self.h, self.dh)
+        a6 = self.acts[-1]
+        capi.dbmp_cnn_linear_backward_weight(st, a6, self.dh, B, FLAT, self.hidden, self.gw[L],
+                                             self.gb[L])
+        capi.dbmp_cnn_linear_backward_data(st, self.dh, B, self.hidden, self.wt[L], FLAT, a6,
+                                           self.dacts[-1])
+        sizes = [IMG >> l for l in range(L)]  # input size of each conv layer
+        for l in range(L - 1, -1, -1):
+            ci, co = CONV[l]
+            x = self.x0 if l == 0 else self.acts[l - 1]
+            s = sizes[l]
+            capi.dbmp_cnn_conv_backward_weight(st, x, self.dacts[l], B, s, s, ci, co, self.gw[l],
+                                               self.gb[l])
+            if l > 0:
+                capi.dbmp_cnn_conv_backward_data(st, self.dacts[l], B, s, s, ci, self.wt[l], co,
+                                                 x, self.dacts[l - 1])
+
+    def loss_and_grad(self, target_codes):
+        """Regression loss of the last forward against coded targets [B, SLOTS, 8]; writes
+        dL/dout and adds the batch-mean loss to self.loss_acc."""
+        B = self._B
+        capi.dbmp_cnn_param_loss(capi.stream_handle(), self.out, target_codes.contiguous(),
+                                 self.w8, B * OUT, 1.0 / (B * SLOTS), self.dout, self.loss_acc)
+
+    def adam(self, lr):
+        capi.dbmp_adam_step(capi.stream_handle(), self.P, self.G, self.m, self.v, self.n_params,
+                            lr, 0.9, 0.999, 1e-8, self.step_count, zero_grad=1)
+        self.cast()
+
+    def train_step(self, img, codes, lr):
+        self.forward(img)
+        self.loss_and_grad(codes)
+        self.backward()
+        self.adam(lr)
+
+    def predict(self, img):
+        """Primitive parameters [B, SLOTS, 8] for targets img [B, 3, 256, 256]."""
+        return decode(self.forward(img))
+
+
+# ------------------------------------------------------------------------------------------
+# Data: (target, parameters after `steps` plain Adam steps from the slot template)
+# ------------------------------------------------------------------------------------------
+def atlas_and_slots(device):
+    atlas = torch.tensor(synth.make_atlas("ss64x16"), device=device)
+    idx = torch.tensor(synth.slot_atlas_index(SLOTS, atlas.shape[0]), device=device)
+    return atlas, idx
+
+
+def generate_pairs(n, steps=500, batch=256, seed=0, device=None, lr=1e-2, log=None):
+    """Returns (targets [n, 3, 256, 256] float32, fitted params [n, SLOTS, 8] float32), both on
+    the device. Fits run `batch` at a time as one batched fit with a captured step."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    atlas, idx = atlas_and_slots(dev)
+    targets = torch.empty(n, 3, IMG, IMG, device=dev)
+    fitted = torch.empty(n, SLOTS, 8, device=dev)
+    R = Renderer(device=dev.index, check=False)
+    t0 = time.perf_counter()
+    for s0 in range(0, n, batch):
+        nb = min(batch, n - s0)
+        tg = synth.target_images_torch(nb, IMG, IMG, 8, seed * 7919 + s0, dev)
+        init = synth.slot_init_params_torch(nb, IMG, IMG, LOG_S_MEAN, LOG_S_STD,
+                                            seed * 104729 + 1 + s0, dev)
+        bf = BatchFitter([(init[i], idx, tg[i]) for i in range(nb)], atlas, lr=lr, renderer=R)
+        bf.capture()
+        bf.run(steps, check_every=steps)
+        targets[s0:s0 + nb] = tg
+        fitted[s0:s0 + nb] = bf.params.view(nb, SLOTS, 8)
+        if log:
+            torch.cuda.synchronize()
+            log("pairs %d/%d  %.1f s  mean psnr %.2f" % (s0 + nb, n, time.perf_counter() - t0,
+                                                        float(np.mean(bf.psnrs()))))
+        del bf
+    torch.cuda.synchronize()
+    return targets, fitted
+
+
+def train(net, targets, fitted, epochs=20, batch=64, lr=1e-3, seed=0, log=None):
+    """Adam on the regression loss; returns the mean loss of the last epoch."""
+    codes = encode(fitted)
+    n = targets.shape[0]
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    last = float("nan")
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(targets.device)
+        net.loss_acc.zero_()
+        k = 0
+        for i in range(0, n - batch + 1, batch):
+            b = perm[i:i + batch]
+            net.train_step(targets[b], codes[b], lr)
+            k += 1
+        last = float(net.loss_acc.item()) / max(k, 1)
+        if log:
+            log("epoch %d loss %.4f" % (ep, last))
+    return last
+
+
+# ------------------------------------------------------------------------------------------
+# Time to PSNR: learned start + <= `learned_steps` steps vs random start + `plain_steps` steps
+# ------------------------------------------------------------------------------------------
+def _psnr(sse, npix):
+    return 10.0 * math.log10(1.0 / max(sse / (3.0 * npix), 1e-30))
+
+
+def evaluate(net, n_targets=64, plain_steps=500, learned_steps=100, seed=10 ** 6, lr=1e-2,
+             log=None):
+    """Per held-out target (seeds disjoint from the training data):
+      plain    slot-template random start, `plain_steps` captured Adam steps: its final PSNR is
+               the bar, its wall time the reference;
+      learned  CNN inference + decoding into the fit's buffers + Adam steps until the PSNR
+               reaches the bar (at most `learned_steps`), unless the CNN start's image error is
+               above the random start's (fallback: the plain fit, same time).
+    Wall times are measured on the device stream around the timed steps (graph replays);
+    the step at which the bar is crossed is found from a second, recorded replay of the same
+    fit. Returns a dict of per-target values and their medians."""
+    dev = net.device
+    atlas, idx = atlas_and_slots(dev)
+    R = Renderer(device=dev.index, check=False)
+    rows = []
+    npix = IMG * IMG
+    for k in range(n_targets):
+        tg = synth.target_images_torch(1, IMG, IMG, 8, seed + k, dev)[0].contiguous()
+        init = synth.slot_init_params_torch(1, IMG, IMG, LOG_S_MEAN, LOG_S_STD,
+                                            seed + 7 * k + 3, dev)[0].contiguous()
+        f = Fitter(init, idx, atlas, tg, lr=lr, renderer=R)
+        f.capture()
+        hist = torch.zeros(max(plain_steps, learned_steps) + 1, device=dev)
+
+        def reset(start):
+            f.params.copy_(start)
+            f.m.zero_()
+            f.v.zero_()
+            f.step_count.zero_()
+            f.grad.zero_()
+
+        def run_timed(start, steps, with_cnn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if with_cnn:
+                start = net.predict(tg[None])[0]
+            reset(start)
+            for _ in range(steps):
+                f.step()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        def run_recorded(start, steps):
+            reset(start)
+            for s in range(steps):
+                f.step()  # the loss recorded at step s is that of the image before update s
+                f.R.mse_loss(hist[s:s + 1])
+            f._render()
+            f.R.backward_mse(f.target, None, out=f.grad, accumulate=True)
+            f.R.mse_loss(hist[steps:steps + 1])
+            f.grad.zero_()
+            return [_psnr(float(x), npix) for x in hist[:steps + 1].cpu()]
+
+        t_plain = run_timed(init, plain_steps, False)
+        ps_plain = run_recorded(init, plain_steps)
+        bar = ps_plain[-1]
+        cnn_start = net.predict(tg[None])[0].clone()
+        t_learned_all = run_timed(None, learned_steps, True)
+        ps_learned = run_recorded(cnn_start, learned_steps)
+        t_infer = _time_inference(net, tg)
+        fallback = ps_learned[0] < ps_plain[0]
+        cross = next((s for s, p in enumerate(ps_learned) if p >= bar), None)
+        per_step = (t_learned_all - t_infer) / learned_steps
+        if fallback:  # inference and the start comparison were paid for, then the plain fit
+            t_learned, reached = t_infer + per_step + t_plain, True
+        elif cross is None:
+            t_learned, reached = float("inf"), False
+        else:
+            t_learned, reached = t_infer + cross * per_step, True
+        rows.append(dict(psnr_bar=bar, psnr_random_start=ps_plain[0],
+                         psnr_cnn_start=ps_learned[0], psnr_learned_end=ps_learned[-1],
+                         steps_to_bar=cross, fallback=fallback, reached=reached,
+                         t_plain=t_plain, t_learned=t_learned, t_infer=t_infer))
+        if log:
+            log("target %d: bar %.2f dB (random start %.2f), cnn start %.2f, %s, t %.2f vs %.2f ms"
+                % (k, bar, ps_plain[0], ps_learned[0],
+                   "fallback" if fallback else ("step %s" % cross),
+                   1e3 * t_learned, 1e3 * t_plain))
+    med = lambda key: float(np.median([r[key] for r in rows]))
+    wins = sum(1 for r in rows if r["t_learned"] < r["t_plain"])
+    return dict(rows=rows, n=len(rows), wins=wins,
+                fallbacks=sum(r["fallback"] for r in rows),
+                median_t_plain_ms=1e3 * med("t_plain"),
+                median_t_learned_ms=1e3 * med("t_learned"),
+                median_t_infer_ms=1e3 * med("t_infer"),
+                median_psnr_bar=med("psnr_bar"),
+                median_psnr_random_start=med("psnr_random_start"),
+                median_psnr_cnn_start=med("psnr_cnn_start"),
+                median_psnr_learned_end=med("psnr_learned_end"))
+
+
+def _time_inference(net, tg, reps=5):
+    net.predict(tg[None])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.predict(tg[None])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps

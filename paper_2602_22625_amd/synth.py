@@ -277,3 +277,85 @@ def make_batch(n_images: int = 64, seed: int = 3000):
         params, idx = init_params(N, S, S, math.log(12.0), 0.5, atlas.shape[0], seed + 10001 + k)
         items.append(dict(H=S, W=S, N=N, target=target, params=params, idx=idx))
     return atlas, items
+
+
+# --------------------------------------------------------------------------------------------
+# Learned-initialiser data: many 256x256 targets and slot-template initial parameters, drawn on
+# the GPU with torch generators (same recipe as target_image / init_params; different random
+# streams, so the values are not those of the NumPy generators).
+# --------------------------------------------------------------------------------------------
+SLOT_GRID = 32        # 32 x 32 cells: slot i starts in cell (i // 32, i % 32)
+SLOT_ATLAS_SEED = 4242
+
+
+def slot_atlas_index(n_slots: int, n_bitmaps: int) -> np.ndarray:
+    """Fixed atlas index per slot, the same for every target (so that slot i means the same
+    kind of primitive across fits)."""
+    return rng(SLOT_ATLAS_SEED).integers(0, n_bitmaps, size=n_slots).astype(np.int32)
+
+
+def target_images_torch(n: int, H: int, W: int, n_ellipses: int, seed: int, device):
+    """[n, 3, H, W] float32 targets on `device`: periodic Gaussian low-pass of white noise
+    (sigma = max(H, W) / 32 px), min-max normalised per channel, then `n_ellipses` opaque
+    ellipses with anti-aliased rims (centre uniform, semi-axes min(H,W) U[0.02, 0.15], angle
+    U[0, pi), colour uniform), clipped to [0, 1]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    noise = torch.randn(n, 3, H, W, generator=g, device=device, dtype=torch.float32)
+    fy = torch.fft.fftfreq(H, device=device)[:, None]
+    fx = torch.fft.rfftfreq(W, device=device)[None, :]
+    sigma = max(H, W) / 32.0
+    resp = torch.exp(-2.0 * math.pi ** 2 * sigma ** 2 * (fx ** 2 + fy ** 2))
+    f = torch.fft.irfft2(torch.fft.rfft2(noise) * resp, s=(H, W))
+    lo = f.amin(dim=(2, 3), keepdim=True)
+    hi = f.amax(dim=(2, 3), keepdim=True)
+    img = (f - lo) / torch.clamp(hi - lo, min=1e-12)
+    L = float(min(H, W))
+    u = torch.rand(n, n_ellipses, 8, generator=g, device=device)
+    cx, cy = u[..., 0] * W, u[..., 1] * H
+    ax = L * (0.02 + 0.13 * u[..., 2])
+    by = L * (0.02 + 0.13 * u[..., 3])
+    phi = math.pi * u[..., 4]
+    col = u[..., 5:8]
+    ys = torch.arange(H, device=device, dtype=torch.float32)[None, :, None]
+    xs = torch.arange(W, device=device, dtype=torch.float32)[None, None, :]
+    for e in range(n_ellipses):
+        c, s = torch.cos(phi[:, e])[:, None, None], torch.sin(phi[:, e])[:, None, None]
+        dx = xs - cx[:, e][:, None, None]
+        dy = ys - cy[:, e][:, None, None]
+        iax, iby = (1.0 / ax[:, e])[:, None, None], (1.0 / by[:, e])[:, None, None]
+        lx = (c * dx + s * dy) * iax
+        ly = (c * dy - s * dx) * iby
+        r = torch.sqrt(lx * lx + ly * ly)
+        gx = c * lx * iax - s * ly * iby
+        gy = s * lx * iax + c * ly * iby
+        grad = torch.sqrt(gx * gx + gy * gy) / torch.clamp(r, min=1e-12)
+        cov = torch.clamp(0.5 - (r - 1.0) / torch.clamp(grad, min=1e-12), 0.0, 1.0)[:, None]
+        img = img + (col[:, e][:, :, None, None] - img) * cov
+    return torch.clamp(img, 0.0, 1.0).contiguous()
+
+
+def slot_init_params_torch(n: int, H: int, W: int, log_s_mean: float, log_s_std: float,
+                           seed: int, device, grid: int = SLOT_GRID):
+    """[n, grid*grid, 8] float32 initial parameters from the slot template: slot i starts at a
+    uniform point of grid cell i (stratified, so positions are still uniform over the image);
+    log_s ~ N(log_s_mean, log_s_std), theta ~ U[0, 2 pi), nu ~ N(0, 1), colour logits of
+    U[1e-3, 1 - 1e-3]. The atlas index of slot i is slot_atlas_index()[i]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    S = grid * grid
+    i = torch.arange(S, device=device)
+    gx, gy = (i % grid).float(), (i // grid).float()
+    u = torch.rand(n, S, 6, generator=g, device=device)
+    z = torch.randn(n, S, 2, generator=g, device=device)
+    p = torch.empty(n, S, 8, device=device)
+    p[..., 0] = (gx + u[..., 0]) * (W / grid)
+    p[..., 1] = (gy + u[..., 1]) * (H / grid)
+    p[..., 2] = log_s_mean + log_s_std * z[..., 0]
+    p[..., 3] = 2.0 * math.pi * u[..., 2]
+    p[..., 4] = z[..., 1]
+    cu = torch.clamp(u[..., 3:6], 1e-3, 1 - 1e-3)
+    p[..., 5:8] = torch.log(cu / (1 - cu))
+    return p

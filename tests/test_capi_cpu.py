@@ -8,10 +8,10 @@ import pytest
 from paper_2602_22625_amd import capi
 
 
-def header_functions():
-    src = open(capi.HEADER).read()
+def header_functions(path=None):
+    src = open(path or capi.HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(dbmp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(dbmp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
@@ -26,8 +26,30 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     lib = capi.load()
-    for n in header_functions():
+    for n in header_functions() + header_functions(capi.HEADER_CNN):
         assert hasattr(lib, n), n
+        assert callable(getattr(capi, n)), n  # the binding has a function of the same name
+
+
+def test_initialiser_header_declares_its_layers():
+    names = header_functions(capi.HEADER_CNN)
+    assert names == sorted([
+        "dbmp_cnn_conv_forward", "dbmp_cnn_conv_backward_data", "dbmp_cnn_conv_backward_weight",
+        "dbmp_cnn_linear_forward", "dbmp_cnn_linear_backward_data",
+        "dbmp_cnn_linear_backward_weight", "dbmp_cnn_cast_weights", "dbmp_cnn_pack_input",
+        "dbmp_cnn_param_loss"])
+
+
+def test_initialiser_host_argument_checks():
+    lib = capi.load()
+    # odd sizes, channel counts not a multiple of 8, missing buffers: rejected before launch
+    assert lib.dbmp_cnn_conv_forward(None, None, 1, 8, 8, 8, None, None, 8, 1, None, None) == -1
+    assert lib.dbmp_cnn_conv_forward(None, 16, 1, 7, 8, 8, 16, None, 8, 1, 16, None) == -1
+    assert lib.dbmp_cnn_conv_forward(None, 16, 1, 8, 8, 3, 16, None, 8, 1, 16, None) == -1
+    assert lib.dbmp_cnn_conv_backward_data(None, 16, 1, 8, 8, 8, 16, 4, None, 16) == -1
+    assert lib.dbmp_cnn_linear_forward(None, 16, 2, 12, 16, None, 4, 0, 16, None) == -1
+    assert lib.dbmp_cnn_param_loss(None, 16, 16, 16, 12, 1.0, 16, None) == -1
+    assert lib.dbmp_cnn_cast_weights(None, None, 1, 1, 1, None, None) == -1
 
 
 def test_host_argument_checks_need_no_device():
