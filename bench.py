@@ -322,6 +322,7 @@ def main():
             "median_psnr_random_start": round(res["median_psnr_random_start"], 3),
             "median_psnr_cnn_start": round(res["median_psnr_cnn_start"], 3),
             "median_psnr_learned_after_100": round(res["median_psnr_learned_end"], 3),
+            "median_psnr_plain_after_100": round(res["median_psnr_plain_same_steps"], 3),
             "training_pairs": args.c4_pairs, "data_generation_s": round(t_data, 2),
             "training_epochs": args.c4_epochs, "training_s": round(t_train, 2),
             "training_final_loss": round(final, 5), "weights": int(net.n_params),

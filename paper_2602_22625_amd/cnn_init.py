@@ -345,6 +345,7 @@ def evaluate(net, n_targets=64, plain_steps=500, learned_steps=100, seed=10 ** 6
             t_learned, reached = t_infer + cross * per_step, True
         rows.append(dict(psnr_bar=bar, psnr_random_start=ps_plain[0],
                          psnr_cnn_start=ps_learned[0], psnr_learned_end=ps_learned[-1],
+                         psnr_plain_same_steps=ps_plain[learned_steps],
                          steps_to_bar=cross, fallback=fallback, reached=reached,
                          t_plain=t_plain, t_learned=t_learned, t_infer=t_infer))
         if log:
@@ -362,7 +363,8 @@ def evaluate(net, n_targets=64, plain_steps=500, learned_steps=100, seed=10 ** 6
                 median_psnr_bar=med("psnr_bar"),
                 median_psnr_random_start=med("psnr_random_start"),
                 median_psnr_cnn_start=med("psnr_cnn_start"),
-                median_psnr_learned_end=med("psnr_learned_end"))
+                median_psnr_learned_end=med("psnr_learned_end"),
+                median_psnr_plain_same_steps=med("psnr_plain_same_steps"))
 
 
 def _time_inference(net, tg, reps=5):

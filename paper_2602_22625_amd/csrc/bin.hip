@@ -110,8 +110,8 @@ __device__ __forceinline__ bool tile_hits(const R &r, int X0, int X1, int Y0, in
 // ------------------------------------------------------------------------------------------
 // k_prep
 // ------------------------------------------------------------------------------------------
-#define PREP_THREADS 1024
-#define PREP_PRIMS 64    // primitives per workgroup: one wave computes records, all walk tiles
+#define PREP_THREADS 256
+#define PREP_PRIMS 16    // primitives per workgroup: 16 lanes compute records, all walk tiles
 #define TILE_LANES 16
 
 // The fields of a record the tile walk needs, kept in LDS between the two phases of k_prep.

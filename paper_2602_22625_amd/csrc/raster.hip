@@ -111,62 +111,24 @@ __device__ __forceinline__ uint64_t support_mask(const PrimRec &r, double U, dou
            __ballot(V < r.Vhi) & valid;
 }
 
-// Bilinear sample of the padded bitmap at (U', V') >= 0 (Supp. Eqs. S1-S3) in two parts, so
-// that the texel loads of the next visited primitive are in flight while the current one is
-// composited: fetch_cell issues the four loads of the floor cell, blend forms M and its
-// derivatives along U' and V'. Lanes outside the support read the bitmap's first texel (always
-// in bounds) and ignore it. Forward and backward call this same code, so both obtain
-// bit-identical alpha (the backward's transmittance recovery relies on it).
-struct Cell {
-    float p00, p01, p10, p11, wu, wv;
-};
-
+// Bilinear sample of the padded bitmap at (U', V') >= 0 (Supp. Eqs. S1-S3): M and its
+// derivatives along U' and V' on the floor cell. Forward and backward call this same code, so
+// both obtain bit-identical alpha (the backward's transmittance recovery relies on it).
 template <typename TexT>
-__device__ __forceinline__ Cell fetch_cell(const TexT *__restrict__ atlas, int tex, int Wp,
-                                           double U, double V, bool in)
+__device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex, int Wp, double U,
+                                         double V, float &M, float &MU, float &MV)
 {
-    Cell c;
-    c.wu = (float)__builtin_amdgcn_fract(U);
-    c.wv = (float)__builtin_amdgcn_fract(V);
-    const int off = in ? (int)V * Wp + (int)U : 0;
-    const TexT *t = atlas + (tex + off);
-    c.p00 = texel<TexT>(t[0]);
-    c.p01 = texel<TexT>(t[1]);
-    c.p10 = texel<TexT>(t[Wp]);
-    c.p11 = texel<TexT>(t[Wp + 1]);
-    return c;
-}
-
-__device__ __forceinline__ void blend(const Cell &c, float &M, float &MU, float &MV)
-{
-    const float d0 = c.p01 - c.p00, d1 = c.p11 - c.p10;
-    const float top = fmaf(c.wu, d0, c.p00);
-    const float bot = fmaf(c.wu, d1, c.p10);
+    const float wu = (float)__builtin_amdgcn_fract(U), wv = (float)__builtin_amdgcn_fract(V);
+    const int iu = (int)U, iv = (int)V;
+    const TexT *t = atlas + (tex + iv * Wp + iu);
+    const float p00 = texel<TexT>(t[0]), p01 = texel<TexT>(t[1]);
+    const float p10 = texel<TexT>(t[Wp]), p11 = texel<TexT>(t[Wp + 1]);
+    const float d0 = p01 - p00, d1 = p11 - p10;
+    const float top = fmaf(wu, d0, p00);
+    const float bot = fmaf(wu, d1, p10);
     MV = bot - top;
-    M = fmaf(c.wv, MV, top);
-    MU = fmaf(c.wv, d1 - d0, d0);
-}
-
-// The next entry of `hits` (lowest position first, or highest first with DESC) whose support
-// covers at least one lane of the wave: its position e, float64 texture coordinates and mask.
-template <bool DESC>
-__device__ __forceinline__ bool next_visit(uint64_t &hits, const PrimRec *__restrict__ s_rec,
-                                           double xd, double yd, uint64_t vmask, int &e,
-                                           double &U, double &V, uint64_t &m)
-{
-    while (hits) {
-        e = DESC ? 63 - __builtin_clzll(hits) : __builtin_ctzll(hits);
-        hits ^= 1ull << e;
-        const PrimRec &r = s_rec[e];
-        U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-        V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-        m = support_mask(r, U, V, vmask);
-        if (m) return true;
-    }
-    e = 0;
-    U = V = 0.0;
-    m = 0;
-    return false;
+    M = fmaf(wv, MV, top);
+    MU = fmaf(wv, d1 - d0, d0);
 }
 
 template <int TS>
@@ -307,27 +269,18 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                 stage_batch<NT>(s_rec, recs, b0, cnt, id_at);
                 __syncthreads();
                 uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
-                // ascending list order (front to back), one visit ahead: the next primitive's
-                // texels load while the current one is composited
-                int e;
-                double U, V;
-                uint64_t m;
-                bool have = next_visit<false>(hits, s_rec, xd, yd, vmask, e, U, V, m);
-                Cell c = fetch_cell<TexT>(atlas, s_rec[e].tex, Wp, U, V,
-                                          __builtin_amdgcn_inverse_ballot_w64(m));
-                while (have) {
-                    int e2;
-                    double U2, V2;
-                    uint64_t m2;
-                    const bool have2 =
-                        next_visit<false>(hits, s_rec, xd, yd, vmask, e2, U2, V2, m2);
-                    const Cell c2 = fetch_cell<TexT>(atlas, s_rec[e2].tex, Wp, U2, V2,
-                                                     __builtin_amdgcn_inverse_ballot_w64(m2));
+                while (hits) {  // ascending list order: front to back
+                    const int e = __builtin_ctzll(hits);
+                    hits &= hits - 1;
+                    const PrimRec &r = s_rec[e];
+                    const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+                    const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+                    const uint64_t m = support_mask(r, U, V, vmask);
+                    if (m == 0) continue;  // no lane of this wave touches the primitive
                     npairs += __popcll(m);
                     if (__builtin_amdgcn_inverse_ballot_w64(m)) {
-                        const PrimRec &r = s_rec[e];
                         float M, MU, MV;
-                        blend(c, M, MU, MV);
+                        bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
                         const float a = r.ka * M;  // Eq. (3)
                         if (T >= DBMP_TAU) { K = b0 + e; TK = T; }
                         const float w = T * a;
@@ -336,10 +289,6 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                         C2 = fmaf(w, r.cb, C2);
                         T = T * (1.f - a);
                     }
-                    have = have2;
-                    e = e2;
-                    m = m2;
-                    c = c2;
                 }
             }
     };
@@ -485,28 +434,21 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             stage_batch<TS * TS>(s_rec, recs, b0, cnt, [&](int j) { return seg[j]; });
             __syncthreads();
             uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
-            // descending list order (back to front), one visit ahead as in the forward
-            int e;
-            double U, V;
-            uint64_t msk;
-            bool have = next_visit<true>(hits, s_rec, xd, yd, vmask, e, U, V, msk);
-            Cell c = fetch_cell<TexT>(atlas, s_rec[e].tex, Wp, U, V,
-                                      __builtin_amdgcn_inverse_ballot_w64(msk));
-            while (have) {
-                int e2;
-                double U2, V2;
-                uint64_t msk2;
-                const bool have2 = next_visit<true>(hits, s_rec, xd, yd, vmask, e2, U2, V2, msk2);
-                const Cell c2 = fetch_cell<TexT>(atlas, s_rec[e2].tex, Wp, U2, V2,
-                                                 __builtin_amdgcn_inverse_ballot_w64(msk2));
+            while (hits) {  // descending list order: back to front
+                const int e = 63 - __builtin_clzll(hits);
+                hits ^= 1ull << e;
                 const PrimRec &r = s_rec[e];
                 const int j = b0 + e;
+                const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+                const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+                const uint64_t msk = support_mask(r, U, V, vmask);
+                if (msk == 0) continue;
                 float d[8];
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < 8; ++q) d[q] = 0.f;
                 if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
                     float M, MU, MV;
-                    blend(c, M, MU, MV);
+                    bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
                     const float a = r.ka * M;
                     const float m = 1.f - a;
                     // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
@@ -540,12 +482,6 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
                 }
                 const float tot = reduce8(d, lane);
                 if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
-                have = have2;
-                e = e2;
-                U = U2;
-                V = V2;
-                msk = msk2;
-                c = c2;
             }
         }
         if (MSE) {
