@@ -71,11 +71,26 @@ int dbmp_cnn_pack_input(void *stream, const float *img, int B, int H, int W, uin
 
 /* Regression loss on rows of 8 parameters, n values (n % 8 == 0): column q contributes
  * weights8[q] (pred - target)^2, except the angle column 3, which contributes
- * weights8[3] (1 - cos(pred - target)). Writes dpred = scale * dL/dpred as bf16 and adds
- * scale * L to *loss (float32; may be NULL). */
+ * weights8[3] (1 - cos(pred - target)). Writes, as bf16,
+ *     dpred[i] = scale * dL/dpred[i] + extra[i] * extra_scale8[i % 8]
+ * (target may be NULL: no regression term; extra may be NULL: no added gradient; it carries a
+ * gradient that reaches the predictions from elsewhere, e.g. an image loss through the
+ * renderer, and extra_scale8 is a HOST array of 8 factors). Adds scale * L to *loss (float32;
+ * may be NULL). */
 int dbmp_cnn_param_loss(void *stream, const float *pred, const float *target,
-                        const float *weights8, long long n, float scale, uint16_t *dpred,
-                        float *loss);
+                        const float *weights8, long long n, float scale, const float *extra,
+                        const float *extra_scale8, uint16_t *dpred, float *loss);
+
+/* Per-column affine coding of n_rows parameter rows [n_rows][8], row r being slot r % slots of
+ * a grid x grid template with cells of `cell` pixels: with centre(r, q) the slot's cell centre
+ * for q = 0 (x) and q = 1 (y) and 0 otherwise, and clip() limiting every column but the angle
+ * (3) to [-clip, clip],
+ *     decode != 0:  out = clip(in) * scale8[q] + bias8[q] + centre(r, q)
+ *     decode == 0:  out = clip((in - bias8[q] - centre(r, q)) / scale8[q]).
+ * scale8 and bias8 are HOST arrays (scale8[q] != 0). in and out may not overlap. */
+int dbmp_cnn_code_params(void *stream, const float *in, long long n_rows, int slots, int grid,
+                         float cell, const float *scale8, const float *bias8, float clip,
+                         int decode, float *out);
 
 #ifdef __cplusplus
 }

@@ -97,3 +97,24 @@ def param_loss(pred, target, weights8, scale):
     L[:, 3] = w[3] * (1.0 - np.cos(d[:, 3]))
     G[:, 3] = w[3] * np.sin(d[:, 3])
     return float(L.sum() * scale), (G * scale).reshape(np.shape(pred))
+
+
+def code_params(x, slots, grid, cell, scale8, bias8, clip, decode):
+    """Per-column affine coding of parameter rows (the initialiser's output coding): row r is
+    slot r % slots of a grid x grid template whose cell centre offsets x (column 0) and y
+    (column 1); every column but the angle (3) is clipped to [-clip, clip] in code space."""
+    x = np.asarray(x, np.float64).reshape(-1, 8)
+    r = np.arange(x.shape[0]) % slots
+    centre = np.zeros_like(x)
+    centre[:, 0] = (r % grid + 0.5) * cell
+    centre[:, 1] = (r // grid + 0.5) * cell
+    s = np.asarray(scale8, np.float64)
+    b = np.asarray(bias8, np.float64)
+    keep = np.arange(8) != 3
+    if decode:
+        t = x.copy()
+        t[:, keep] = np.clip(t[:, keep], -clip, clip)
+        return t * s + b + centre
+    t = (x - b - centre) / s
+    t[:, keep] = np.clip(t[:, keep], -clip, clip)
+    return t

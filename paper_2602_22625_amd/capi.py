@@ -75,7 +75,8 @@ def load():
         "dbmp_cnn_linear_backward_weight": ([P, P, P, I, I, I, P, P], I),
         "dbmp_cnn_cast_weights": ([P, P, I, I, I, P, P], I),
         "dbmp_cnn_pack_input": ([P, P, I, I, I, P], I),
-        "dbmp_cnn_param_loss": ([P, P, P, P, LL, F, P, P], I),
+        "dbmp_cnn_param_loss": ([P, P, P, P, LL, F, P, P, P, P], I),
+        "dbmp_cnn_code_params": ([P, P, LL, I, I, F, P, P, F, I, P], I),
     })
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -257,7 +258,26 @@ def dbmp_cnn_pack_input(stream, img, B, H, W, x):
                 "dbmp_cnn_pack_input")
 
 
-def dbmp_cnn_param_loss(stream, pred, target, weights8, n, scale, dpred, loss):
+def _host8(v):
+    if v is None:
+        return None
+    arr = (ctypes.c_float * 8)(*[float(x) for x in v])
+    return ctypes.cast(arr, ctypes.c_void_p), arr
+
+
+def dbmp_cnn_param_loss(stream, pred, target, weights8, n, scale, dpred, loss, extra=None,
+                        extra_scale8=None):
+    xs = _host8(extra_scale8)
     return _cnn(load().dbmp_cnn_param_loss(stream, ptr(pred), ptr(target), ptr(weights8), int(n),
-                                           float(scale), ptr(dpred), ptr(loss)),
+                                           float(scale), ptr(extra), xs[0] if xs else None,
+                                           ptr(dpred), ptr(loss)),
                 "dbmp_cnn_param_loss")
+
+
+def dbmp_cnn_code_params(stream, src, n_rows, slots, grid, cell, scale8, bias8, clip, decode,
+                         out):
+    sc, bi = _host8(scale8), _host8(bias8)
+    return _cnn(load().dbmp_cnn_code_params(stream, ptr(src), int(n_rows), int(slots), int(grid),
+                                            float(cell), sc[0], bi[0], float(clip), int(decode),
+                                            ptr(out)),
+                "dbmp_cnn_code_params")

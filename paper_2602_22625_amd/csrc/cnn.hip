@@ -333,29 +333,39 @@ __global__ void k_pack(const float *__restrict__ img, int B, int H, int W, u16 *
 
 // Parameter regression loss over rows of 8 values: weighted squared error per column, except
 // the angle column (3), which uses w (1 - cos(pred - target)) so that full turns cost nothing.
-// Writes dL/dpred * scale as bf16 and adds the weighted loss sum * scale to *loss.
+// Writes dpred = scale * dL/dpred (+ extra[i] * xs[column], a gradient reaching the codes from
+// elsewhere, e.g. through the renderer) as bf16 and adds the weighted loss sum * scale to *loss.
+struct Col8 {
+    float v[8];
+};
+
 __global__ void __launch_bounds__(256) k_param_loss(const float *__restrict__ pred,
                                                     const float *__restrict__ tgt,
                                                     const float *__restrict__ w, long long n,
-                                                    float scale, u16 *__restrict__ dpred,
+                                                    float scale, const float *__restrict__ extra,
+                                                    Col8 xs, u16 *__restrict__ dpred,
                                                     float *__restrict__ loss)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.f;
     if (i < n) {
         const int q = (int)(i & 7);
-        const float d = pred[i] - tgt[i];
-        float g;
-        if (q == 3) {
-            float sn, cs;
-            __sincosf(d, &sn, &cs);
-            l = w[q] * (1.f - cs);
-            g = w[q] * sn;
-        } else {
-            l = w[q] * d * d;
-            g = 2.f * w[q] * d;
+        float g = 0.f;
+        if (tgt) {
+            const float d = pred[i] - tgt[i];
+            if (q == 3) {
+                float sn, cs;
+                __sincosf(d, &sn, &cs);
+                l = w[q] * (1.f - cs);
+                g = w[q] * sn;
+            } else {
+                l = w[q] * d * d;
+                g = 2.f * w[q] * d;
+            }
         }
-        dpred[i] = f2bf(g * scale);
+        g *= scale;
+        if (extra) g = fmaf(extra[i], xs.v[q], g);
+        dpred[i] = f2bf(g);
     }
     __shared__ float part[256];
     part[threadIdx.x] = l;
@@ -365,6 +375,36 @@ __global__ void __launch_bounds__(256) k_param_loss(const float *__restrict__ pr
         __syncthreads();
     }
     if (threadIdx.x == 0 && loss) unsafeAtomicAdd(loss, part[0] * scale);
+}
+
+// Per-column affine coding of parameter rows (row r is slot r % slots of a grid x grid
+// template): decode  p = clip(t) * scale[q] + bias[q] + centre(slot, q),
+//          encode  t = clip((p - bias[q] - centre(slot, q)) / scale[q]),
+// where centre is the slot's cell centre for x (q = 0) and y (q = 1) and 0 otherwise, and clip
+// limits to [-clip, clip] every column but the angle (3).
+struct Coding {
+    Col8 scale, bias;
+    int slots, grid;
+    float cell, clip;
+};
+
+__global__ void k_code(const float *__restrict__ in, long long n, Coding c, int decode,
+                       float *__restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int q = (int)(i & 7);
+    const int slot = (int)((i >> 3) % c.slots);
+    const float centre = q == 0 ? ((slot % c.grid) + 0.5f) * c.cell
+                                : (q == 1 ? ((slot / c.grid) + 0.5f) * c.cell : 0.f);
+    const float lim = q == 3 ? 3.0e38f : c.clip;
+    if (decode) {
+        const float t = fminf(fmaxf(in[i], -lim), lim);
+        out[i] = fmaf(t, c.scale.v[q], c.bias.v[q] + centre);
+    } else {
+        const float t = (in[i] - c.bias.v[q] - centre) / c.scale.v[q];
+        out[i] = fminf(fmaxf(t, -lim), lim);
+    }
 }
 
 }  // namespace dbmp_cnn
@@ -479,13 +519,42 @@ int dbmp_cnn_pack_input(void *stream, const float *img, int B, int H, int W, uin
 }
 
 int dbmp_cnn_param_loss(void *stream, const float *pred, const float *target,
-                        const float *weights8, long long n, float scale, uint16_t *dpred,
-                        float *loss)
+                        const float *weights8, long long n, float scale, const float *extra,
+                        const float *extra_scale8, uint16_t *dpred, float *loss)
 {
-    if (!pred || !target || !weights8 || !dpred || n < 0 || (n & 7)) return DBMP_CNN_EINVAL;
+    if (!pred || (target && !weights8) || (extra && !extra_scale8) || !dpred || n < 0 ||
+        (n & 7))
+        return DBMP_CNN_EINVAL;
     if (n == 0) return DBMP_CNN_OK;
+    Col8 xs{};
+    if (extra)
+        for (int q = 0; q < 8; ++q) xs.v[q] = extra_scale8[q];
     k_param_loss<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
-        pred, target, weights8, n, scale, dpred, loss);
+        pred, target, weights8, n, scale, extra, xs, dpred, loss);
+    return status(hipGetLastError());
+}
+
+int dbmp_cnn_code_params(void *stream, const float *in, long long n_rows, int slots, int grid,
+                         float cell, const float *scale8, const float *bias8, float clip,
+                         int decode, float *out)
+{
+    if (!in || !out || !scale8 || !bias8 || n_rows < 0 || slots < 1 || grid < 1 || !(clip > 0.f))
+        return DBMP_CNN_EINVAL;
+    for (int q = 0; q < 8; ++q)
+        if (scale8[q] == 0.f) return DBMP_CNN_EINVAL;
+    if (n_rows == 0) return DBMP_CNN_OK;
+    Coding c{};
+    for (int q = 0; q < 8; ++q) {
+        c.scale.v[q] = scale8[q];
+        c.bias.v[q] = bias8[q];
+    }
+    c.slots = slots;
+    c.grid = grid;
+    c.cell = cell;
+    c.clip = clip;
+    const long long n = n_rows * 8;
+    k_code<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(in, n, c, decode ? 1 : 0,
+                                                                        out);
     return status(hipGetLastError());
 }
 

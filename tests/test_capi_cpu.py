@@ -37,7 +37,7 @@ def test_initialiser_header_declares_its_layers():
         "dbmp_cnn_conv_forward", "dbmp_cnn_conv_backward_data", "dbmp_cnn_conv_backward_weight",
         "dbmp_cnn_linear_forward", "dbmp_cnn_linear_backward_data",
         "dbmp_cnn_linear_backward_weight", "dbmp_cnn_cast_weights", "dbmp_cnn_pack_input",
-        "dbmp_cnn_param_loss"])
+        "dbmp_cnn_param_loss", "dbmp_cnn_code_params"])
 
 
 def test_initialiser_host_argument_checks():
@@ -48,7 +48,14 @@ def test_initialiser_host_argument_checks():
     assert lib.dbmp_cnn_conv_forward(None, 16, 1, 8, 8, 3, 16, None, 8, 1, 16, None) == -1
     assert lib.dbmp_cnn_conv_backward_data(None, 16, 1, 8, 8, 8, 16, 4, None, 16) == -1
     assert lib.dbmp_cnn_linear_forward(None, 16, 2, 12, 16, None, 4, 0, 16, None) == -1
-    assert lib.dbmp_cnn_param_loss(None, 16, 16, 16, 12, 1.0, 16, None) == -1
+    assert lib.dbmp_cnn_param_loss(None, 16, 16, 16, 12, 1.0, None, None, 16, None) == -1
+    assert lib.dbmp_cnn_param_loss(None, 16, 16, None, 16, 1.0, None, None, 16, None) == -1
+    s8 = (ctypes.c_float * 8)(*([1.0] * 8))
+    z8 = (ctypes.c_float * 8)(*([0.0] * 8))
+    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 8.0, ctypes.cast(z8, ctypes.c_void_p),
+                                    ctypes.cast(s8, ctypes.c_void_p), 4.0, 1, 16) == -1
+    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 8.0, ctypes.cast(s8, ctypes.c_void_p),
+                                    ctypes.cast(s8, ctypes.c_void_p), 0.0, 1, 16) == -1
     assert lib.dbmp_cnn_cast_weights(None, None, 1, 1, 1, None, None) == -1
 
 

@@ -162,3 +162,40 @@ def test_param_loss_matches_oracle():
     # dpred is stored in bf16: within half an ulp of bf16 (2^-9 relative) plus the float32
     # rounding of the sine
     assert np.allclose(dp.float().cpu().numpy(), G, rtol=2 ** -8, atol=1e-6)
+
+
+def test_param_loss_added_gradient_and_no_target():
+    g = np.random.default_rng(51)
+    p = g.standard_normal((64, 8)).astype(np.float32)
+    t = g.standard_normal((64, 8)).astype(np.float32)
+    x = g.standard_normal((64, 8)).astype(np.float32)
+    w = np.ones(8, np.float32)
+    xs = [0.5, 1, 2, 4, 0.25, 1, 1, 3]
+    dp = torch.empty(64, 8, device="cuda", dtype=torch.bfloat16)
+    P, X = torch.tensor(p, device="cuda"), torch.tensor(x, device="cuda")
+    capi.dbmp_cnn_param_loss(st(), P, torch.tensor(t, device="cuda"),
+                             torch.tensor(w, device="cuda"), p.size, 0.5, dp, None, X, xs)
+    torch.cuda.synchronize()
+    _, G = co.param_loss(p, t, w, 0.5)
+    assert np.allclose(dp.float().cpu().numpy(), G + x * np.array(xs), rtol=2 ** -8, atol=1e-6)
+    capi.dbmp_cnn_param_loss(st(), P, None, None, p.size, 0.5, dp, None, X, xs)
+    torch.cuda.synchronize()
+    assert np.allclose(dp.float().cpu().numpy(), x * np.array(xs), rtol=2 ** -8, atol=0)
+
+
+def test_code_params_matches_oracle():
+    g = np.random.default_rng(52)
+    s8 = [8, 8, 0.5, 1, 2, 2, 2, 2]
+    b8 = [0, 0, 2.48, 0, 0, 0, 0, 0]
+    t = g.uniform(-6, 6, (3 * 1024, 8)).astype(np.float32)
+    T = torch.tensor(t, device="cuda")
+    out = torch.empty_like(T)
+    capi.dbmp_cnn_code_params(st(), T, t.shape[0], 1024, 32, 8.0, s8, b8, 4.0, 1, out)
+    torch.cuda.synchronize()
+    ref = co.code_params(t, 1024, 32, 8.0, s8, b8, 4.0, True)
+    assert np.allclose(out.cpu().numpy(), ref, rtol=1e-6, atol=1e-5)
+    back = torch.empty_like(T)
+    capi.dbmp_cnn_code_params(st(), out, t.shape[0], 1024, 32, 8.0, s8, b8, 4.0, 0, back)
+    torch.cuda.synchronize()
+    ref2 = co.code_params(ref, 1024, 32, 8.0, s8, b8, 4.0, False)
+    assert np.allclose(back.cpu().numpy(), ref2, rtol=1e-5, atol=1e-5)

@@ -94,13 +94,13 @@ def test_network_forward_backward_layer_by_layer():
 
 def test_learned_start_gains_over_random_start():
     """A small version of the whole procedure: 512 (target, 100-step fit) pairs, a short
-    training, 8 held-out targets. The trained network's start must beat the random start it
-    replaces (initial PSNR), and after the same number of Adam steps (50) the learned fit must
-    be ahead of the plain one."""
+    training on the regression plus the image loss through the renderer, 8 held-out targets.
+    The trained network's start must beat the random start it replaces (initial PSNR), and
+    after the same number of Adam steps (50) the learned fit must be ahead of the plain one."""
     from paper_2602_22625_amd import cnn_init as ci
     tg, fitted = ci.generate_pairs(512, steps=100, batch=256, seed=1)
     net = ci.InitNet(seed=0)
-    ci.train(net, tg, fitted, epochs=12, batch=64, lr=2e-3)
+    ci.train(net, tg, fitted, epochs=12, batch=64, lr=2e-3, image_weight=1.0)
     res = ci.evaluate(net, n_targets=8, plain_steps=100, learned_steps=50, seed=10 ** 7)
     print({k: v for k, v in res.items() if k != "rows"})
     assert res["median_psnr_cnn_start"] > res["median_psnr_random_start"] + 1.0

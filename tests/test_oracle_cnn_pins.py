@@ -101,3 +101,19 @@ def test_param_loss_gradient_and_angle_periodicity():
     p2 = p.copy()
     p2[:, 3] += 2 * math.pi  # a full turn of the angle costs nothing
     assert abs(co.param_loss(p2, t, w, 0.25)[0] - L) < 1e-12
+
+
+def test_code_params_round_trip_and_cell_centres():
+    g = np.random.default_rng(5)
+    s8 = [8, 8, 0.5, 1, 2, 2, 2, 2]
+    b8 = [0, 0, 2.5, 0, 0, 0, 0, 0]
+    t = g.uniform(-3, 3, (2 * 16, 8))
+    p = co.code_params(t, 16, 4, 8.0, s8, b8, 4.0, True)
+    assert np.allclose(co.code_params(p, 16, 4, 8.0, s8, b8, 4.0, False), t, atol=1e-12)
+    # a zero code sits at the slot's cell centre with the mean scale
+    z = co.code_params(np.zeros((16, 8)), 16, 4, 8.0, s8, b8, 4.0, True)
+    assert z[5, 0] == (5 % 4 + 0.5) * 8 and z[5, 1] == (5 // 4 + 0.5) * 8 and z[5, 2] == 2.5
+    # clipping applies to every column but the angle
+    big = np.full((1, 8), 10.0)
+    c = co.code_params(big, 16, 4, 8.0, s8, b8, 4.0, True)
+    assert c[0, 3] == 10.0 and c[0, 4] == 8.0
