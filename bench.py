@@ -2,8 +2,8 @@
 """Benchmark of the differentiable bitmap-primitive rasteriser on one MI355X.
 
 A step is one plain Adam iteration on the 512x512 workload (4,096 primitives, 16 star/stroke
-bitmaps of 64x64 fp32, 16x16 tiles): per-primitive setup and binning, forward compositing, MSE
-gradient, backward, Adam, replayed from a captured HIP graph. Inputs are resident in HBM before
+bitmaps of 64x64 fp32, 16x16 tiles): per-primitive setup and binning, then forward compositing,
+MSE gradient and backward in one fused launch, then Adam, replayed from a captured HIP graph. Inputs are resident in HBM before
 the timed region. The value is primitive-pixel evaluations per second over forward + backward:
 (pixel, primitive) pairs evaluated by the timed steps (counted on the device, one popcount per
 wave and primitive; the count is pinned in the tests against an exact host count) divided by
@@ -147,6 +147,10 @@ def main():
     def bwd():
         R.backward_mse(fit.target, None, out=fit.grad, accumulate=True)
 
+    def fused():
+        R.render_mse(fit.params, idx, None, H, W, fit.target, fit.bg, 1.0, wl.tile,
+                     image=fit.image, out=fit.grad, accumulate=True)
+
     def adam():
         capi.dbmp_adam_step(capi.stream_handle(), fit.params, fit.grad, fit.m, fit.v,
                             fit.params.numel(), 1e-2, 0.9, 0.999, 1e-8, fit.step_count,
@@ -174,31 +178,35 @@ def main():
     ppl = capi.dbmp_support_pairs(R.ctx, capi.stream_handle(), reset=1) / (reps + 1)
     t_bwd = timed(bwd)
     t_adam = timed(adam)
+    t_fused = timed(fused)
     k_fwd = kernel_time(0, fwd)
     k_bwd = kernel_time(1, bwd)
+    k_fused = kernel_time(0, fused)
     fit.restore(snap)
-    bwd_flops = ppl * metrics.BWD_FLOP_PER_PAIR
-    bwd_tflops = bwd_flops / k_bwd * 1e-12
-    log("per call: fwd(bin+raster) %.1f us, bwd(+mse) %.1f us, adam %.1f us, pairs %.0f; "
-        "kernels: k_raster_fwd %.1f us, k_raster_bwd %.1f us"
-        % (t_fwd * 1e6, t_bwd * 1e6, t_adam * 1e6, ppl, k_fwd * 1e6, k_bwd * 1e6))
+    flop_pair = metrics.FWD_FLOP_PER_PAIR + metrics.BWD_FLOP_PER_PAIR
+    step_tflops = ppl * flop_pair / k_fused * 1e-12
+    log("per call: fwd(bin+raster) %.1f us, bwd(+mse) %.1f us, fused step %.1f us, adam %.1f us, "
+        "pairs %.0f; kernels: k_raster_fwd %.1f us, k_raster_bwd %.1f us, fused %.1f us"
+        % (t_fwd * 1e6, t_bwd * 1e6, t_fused * 1e6, t_adam * 1e6, ppl, k_fwd * 1e6,
+           k_bwd * 1e6, k_fused * 1e6))
     longest = R.longest_list()
-    bwd_bytes = metrics.bwd_algorithmic_bytes(H, W, N, atlas.numel() * 4)
-    traffic = measured_traffic("k_raster_bwd_512sq_4096prims_traffic.md")
+    step_bytes = metrics.fused_algorithmic_bytes(H, W, N, atlas.numel() * 4)
+    traffic = measured_traffic("k_raster_fused_512sq_4096prims_traffic.md")
     roofline = {
-        "kernel": "k_raster_bwd (MSE gradient fused, accumulating into the zeroed gradient)",
+        "kernel": "k_raster_fwd<16, float, false, true>: forward and MSE backward of a fit step "
+                  "in one launch (the timed steps' raster kernel)",
         "bound": "alu",
-        "achieved": round(bwd_tflops, 4),
+        "achieved": round(step_tflops, 4),
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": round(bwd_tflops / PEAK_FP32_TFLOPS, 5),
-        "frac_of_nonpacked_fp32_peak": round(bwd_tflops / 78.6, 5),
-        "flop_per_pair": metrics.BWD_FLOP_PER_PAIR,
+        "frac": round(step_tflops / PEAK_FP32_TFLOPS, 5),
+        "frac_of_nonpacked_fp32_peak": round(step_tflops / 78.6, 5),
+        "flop_per_pair": flop_pair,
         "pairs_per_launch": round(ppl),
-        "avg_launch_us": round(k_bwd * 1e6, 2),
-        "hbm_algorithmic_bytes": round(bwd_bytes),
-        "hbm_algorithmic_GBps": round(bwd_bytes / k_bwd * 1e-9, 2),
-        "hbm_frac": round(bwd_bytes / k_bwd * 1e-9 / PEAK_HBM_GBS, 5),
+        "avg_launch_us": round(k_fused * 1e6, 2),
+        "hbm_algorithmic_bytes": round(step_bytes),
+        "hbm_algorithmic_GBps": round(step_bytes / k_fused * 1e-9, 2),
+        "hbm_frac": round(step_bytes / k_fused * 1e-9 / PEAK_HBM_GBS, 5),
         "traffic": traffic,
     }
 
@@ -206,8 +214,11 @@ def main():
         "adam_iters_per_s_graph": round(args.steps / wall, 2),
         "per_call_us_back_to_back": {"fwd_incl_binning": round(t_fwd * 1e6, 2),
                                      "bwd_incl_mse": round(t_bwd * 1e6, 2),
+                                     "fused_step_incl_binning": round(t_fused * 1e6, 2),
                                      "adam": round(t_adam * 1e6, 2)},
-        "kernel_us": {"k_raster_fwd": round(k_fwd * 1e6, 2), "k_raster_bwd": round(k_bwd * 1e6, 2)},
+        "kernel_us": {"k_raster_fwd": round(k_fwd * 1e6, 2), "k_raster_bwd": round(k_bwd * 1e6, 2),
+                      "k_raster_fwd_fused": round(k_fused * 1e6, 2)},
+        "separate_bwd_kernel_tflops": round(ppl * metrics.BWD_FLOP_PER_PAIR / k_bwd * 1e-12, 4),
         "fwd_plus_bwd_evals_per_s_eager": round(ppl / (t_fwd + t_bwd)),
         "psnr_after_steps": round(fit.psnr(), 3),
         "longest_tile_list": int(longest),
@@ -397,6 +408,9 @@ def profile_driver(args, synth, capi, Renderer, np, torch, dev):
     for k in range(args.steps):
         R.render(P, I, None, wl.H, wl.W, None, 1.0, wl.tile, image=img, with_alpha=False)
         R.backward_mse(T, None, out=out, accumulate=True)
+    for k in range(args.steps):  # the fused fit step (forward + MSE backward, one launch)
+        R.render_mse(P, I, None, wl.H, wl.W, T, None, 1.0, wl.tile, image=img, out=out,
+                     accumulate=True)
     torch.cuda.synchronize()
     R.check()
     src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -404,7 +418,8 @@ def profile_driver(args, synth, capi, Renderer, np, torch, dev):
     torch.cuda.synchronize()
     dst.copy_(src)  # 256 MiB read + 256 MiB write
     torch.cuda.synchronize()
-    log("profile driver: %s, %d forward+backward(MSE) passes, then a 256 MiB copy" %
+    log("profile driver: %s, %d forward+backward(MSE) passes, as many fused steps, then a 256 MiB "
+        "copy" %
         (args.profile, args.steps))
 
 

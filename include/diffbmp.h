@@ -157,6 +157,25 @@ int dbmp_render_backward(dbmp_ctx *ctx, dbmp_stream stream, const float *dL_dima
 int dbmp_render_backward_mse(dbmp_ctx *ctx, dbmp_stream stream, const float *target,
                              const float *dL_dalpha, float *dL_dparams, int accumulate);
 
+/*
+ * One fit step's render and MSE backward in one launch per stage (the forward of dbmp_render,
+ * then in the same workgroups the backward of dbmp_render_backward_mse, reusing the image, the
+ * per-pixel state and the staged primitive records while they are still on chip):
+ *   arguments as dbmp_render (alpha is not produced), plus
+ *   target       device float32 [3, H, W];
+ *   image        out, the forward's image, as dbmp_render;
+ *   dL_dparams   out, device float32 [N, 8]: dL/dparams of L = mean((I - target)^2), added to
+ *                the buffer (accumulate != 0) or written (accumulate == 0).
+ * Afterwards dbmp_mse_loss reports the loss and the context holds the state of a forward (a
+ * later dbmp_render_backward* reuses it). Results equal those of the two separate calls (the
+ * gradient up to the order of its float atomics).
+ */
+int dbmp_render_mse(dbmp_ctx *ctx, dbmp_stream stream, const float *params,
+                    const int32_t *atlas_idx, int N, const void *atlas, int B, int Hb, int Wb,
+                    int atlas_dtype, int H, int W, const float *bg, int bg_per_pixel,
+                    float alpha_max, int tile, const float *target, float *image,
+                    float *dL_dparams, int accumulate);
+
 /* Sum over pixels and channels of (I - target)^2 of each image of the last
  * dbmp_render_backward_mse, written to out[0 .. n_images) (device float32). Asynchronous. */
 int dbmp_mse_loss(dbmp_ctx *ctx, dbmp_stream stream, float *out);
@@ -181,6 +200,15 @@ int dbmp_render_batched(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
                         const int32_t *atlas_idx, const void *atlas, int B, int Hb, int Wb,
                         int atlas_dtype, const float *bg, float alpha_max, int tile,
                         float *image, float *alpha);
+
+/* dbmp_render_mse over a batch of images (dbmp_render_batched's layout; each image's loss is the
+ * mean over its own 3HW values). */
+int dbmp_render_batched_mse(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
+                            const dbmp_image_desc *descs, const float *params,
+                            const int32_t *atlas_idx, const void *atlas, int B, int Hb, int Wb,
+                            int atlas_dtype, const float *bg, float alpha_max, int tile,
+                            const float *target, float *image, float *dL_dparams,
+                            int accumulate);
 
 /* Synchronises `stream` and reports the device-side errors raised by any forward since the
  * previous dbmp_check: DBMP_EOVERFLOW (a tile list did not fit; that forward's image is not

@@ -56,6 +56,8 @@ def load():
         "dbmp_set_atlas": ([P, P, P, I, I, I, I], I),
         "dbmp_render": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P], I),
         "dbmp_render_backward": ([P, P, P, P, P], I),
+        "dbmp_render_mse": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P, P, I], I),
+        "dbmp_render_batched_mse": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P, P, I], I),
         "dbmp_render_backward_mse": ([P, P, P, P, P, I], I),
         "dbmp_mse_loss": ([P, P, P], I),
         "dbmp_render_batched": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P], I),
@@ -146,6 +148,28 @@ def dbmp_render(ctx, stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dtype
                                         ptr(atlas), int(B), int(Hb), int(Wb), int(atlas_dtype),
                                         int(H), int(W), ptr(bg), int(bg_per_pixel),
                                         float(alpha_max), int(tile), ptr(image), ptr(alpha)))
+
+
+def dbmp_render_mse(ctx, stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dtype, H, W, bg,
+                    bg_per_pixel, alpha_max, tile, target, image, dL_dparams, accumulate):
+    return _chk(ctx, load().dbmp_render_mse(ctx, stream, ptr(params), ptr(atlas_idx), int(N),
+                                            ptr(atlas), int(B), int(Hb), int(Wb),
+                                            int(atlas_dtype), int(H), int(W), ptr(bg),
+                                            int(bg_per_pixel), float(alpha_max), int(tile),
+                                            ptr(target), ptr(image), ptr(dL_dparams),
+                                            int(accumulate)))
+
+
+def dbmp_render_batched_mse(ctx, stream, descs, params, atlas_idx, atlas, B, Hb, Wb,
+                            atlas_dtype, bg, alpha_max, tile, target, image, dL_dparams,
+                            accumulate):
+    arr = (ImageDesc * len(descs))(*descs)
+    return _chk(ctx, load().dbmp_render_batched_mse(ctx, stream, len(descs), arr,
+                                                    ptr(params), ptr(atlas_idx), ptr(atlas),
+                                                    int(B), int(Hb), int(Wb), int(atlas_dtype),
+                                                    ptr(bg), float(alpha_max), int(tile),
+                                                    ptr(target), ptr(image), ptr(dL_dparams),
+                                                    int(accumulate)))
 
 
 def dbmp_render_backward(ctx, stream, dL_dimage, dL_dalpha, dL_dparams):

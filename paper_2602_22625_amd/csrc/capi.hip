@@ -175,10 +175,17 @@ void take_timing(dbmp_ctx *c, int stage, hipStream_t st, RasterArgs &a)
 }
 
 // Shared body of dbmp_render and dbmp_render_batched. atlas == NULL: the context's atlas.
+// MSE fit step fused into the forward (dbmp_render_mse): the target and the gradient buffer.
+struct FuseMse {
+    const float *target = nullptr;
+    float *dparams = nullptr;
+    bool accumulate = false;
+};
+
 int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> &descs,
                 const float *params, const int32_t *atlas_idx, const void *atlas, int B, int Hb,
                 int Wb, int dtype, const float *bg, int bg_pp, float alpha_max, int tile,
-                float *image, float *alpha)
+                float *image, float *alpha, const FuseMse &fuse = FuseMse())
 {
     if (!bg) return fail(c, DBMP_EINVAL, "bg is NULL");
     if (!(alpha_max > 0.f && alpha_max <= 1.f))
@@ -225,6 +232,8 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     }
     if (n_rows > 0 && (!params || !atlas_idx))
         return fail(c, DBMP_EINVAL, "params / atlas_idx is NULL");
+    if (fuse.target && n_rows > 0 && !fuse.dparams)
+        return fail(c, DBMP_EINVAL, "dL_dparams is NULL");
     if (n_rows >= INT_MAX) return fail(c, DBMP_EINVAL, "too many primitives");
     if ((long long)tiles * c->list_cap >= (1LL << 40))
         return fail(c, DBMP_EINVAL, "tile lists too large");
@@ -290,8 +299,18 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.order = (const int *)c->order.p;
     ra.queue = (int *)c->queue.p;
     take_timing(c, 0, st, ra);
+    if (fuse.target) {  // dparams checked before anything was launched
+        ra.target = fuse.target;
+        ra.dparams = fuse.dparams;
+        if (!fuse.accumulate && n_rows > 0) {
+            e = launch_fill0(fuse.dparams, n_rows * 8, st);
+            if (e != hipSuccess) return hip_fail(c, e, "gradient clear");
+        }
+    }
     e = launch_raster_fwd(ra, st);
     ra.ev_start = ra.ev_stop = nullptr;
+    ra.target = nullptr;  // the saved state is that of a plain forward
+    ra.dparams = nullptr;
     if (e != hipSuccess) {
         // the appended counts were not consumed: clear them for the next forward
         (void)hipStreamSynchronize(st);
@@ -299,7 +318,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
         return hip_fail(c, e, "forward launch");
     }
     c->have_fwd = true;
-    c->have_loss = false;
+    c->have_loss = fuse.target != nullptr;
     c->n_rows = n_rows;
     c->err.clear();
     return DBMP_OK;
@@ -435,6 +454,46 @@ int dbmp_render_batched(dbmp_ctx *c, dbmp_stream stream, int n_images,
     std::vector<dbmp_image_desc> d(descs, descs + n_images);
     return render_impl(c, (hipStream_t)stream, d, params, atlas_idx, atlas, B, Hb, Wb,
                        atlas_dtype, bg, 0, alpha_max, tile, image, alpha);
+}
+
+int dbmp_render_mse(dbmp_ctx *c, dbmp_stream stream, const float *params,
+                    const int32_t *atlas_idx, int N, const void *atlas, int B, int Hb, int Wb,
+                    int atlas_dtype, int H, int W, const float *bg, int bg_per_pixel,
+                    float alpha_max, int tile, const float *target, float *image,
+                    float *dL_dparams, int accumulate)
+{
+    if (!c) return DBMP_EINVAL;
+    if (N < 0 || H < 1 || W < 1) return fail(c, DBMP_EINVAL, "bad N / H / W");
+    if (!target) return fail(c, DBMP_EINVAL, "target is NULL");
+    DeviceGuard g(c->device);
+    std::vector<dbmp_image_desc> d(1);
+    d[0].H = H; d[0].W = W; d[0].N = N; d[0].reserved = 0;
+    d[0].prim_offset = 0; d[0].pixel_offset = 0;
+    FuseMse f;
+    f.target = target;
+    f.dparams = dL_dparams;
+    f.accumulate = accumulate != 0;
+    return render_impl(c, (hipStream_t)stream, d, params, atlas_idx, atlas, B, Hb, Wb,
+                       atlas_dtype, bg, bg_per_pixel ? 1 : 0, alpha_max, tile, image, nullptr, f);
+}
+
+int dbmp_render_batched_mse(dbmp_ctx *c, dbmp_stream stream, int n_images,
+                            const dbmp_image_desc *descs, const float *params,
+                            const int32_t *atlas_idx, const void *atlas, int B, int Hb, int Wb,
+                            int atlas_dtype, const float *bg, float alpha_max, int tile,
+                            const float *target, float *image, float *dL_dparams, int accumulate)
+{
+    if (!c) return DBMP_EINVAL;
+    if (n_images < 1 || !descs) return fail(c, DBMP_EINVAL, "need n_images >= 1 descriptors");
+    if (!target) return fail(c, DBMP_EINVAL, "target is NULL");
+    DeviceGuard g(c->device);
+    std::vector<dbmp_image_desc> d(descs, descs + n_images);
+    FuseMse f;
+    f.target = target;
+    f.dparams = dL_dparams;
+    f.accumulate = accumulate != 0;
+    return render_impl(c, (hipStream_t)stream, d, params, atlas_idx, atlas, B, Hb, Wb,
+                       atlas_dtype, bg, 0, alpha_max, tile, image, nullptr, f);
 }
 
 int dbmp_render_backward(dbmp_ctx *c, dbmp_stream stream, const float *dL_dimage,

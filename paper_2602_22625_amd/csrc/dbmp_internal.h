@@ -162,6 +162,7 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st);
 hipError_t launch_order(const int *tile_count, int n_tiles, int *order, hipStream_t st);
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);
+hipError_t launch_fill0(float *p, long long n, hipStream_t st);
 hipError_t launch_loss_sum(const float *loss_tile, const ImgDev *imgs, int n_images, float *out,
                            hipStream_t st);
 

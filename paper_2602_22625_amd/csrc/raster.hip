@@ -112,15 +112,13 @@ __device__ __forceinline__ uint64_t support_mask(const PrimRec &r, double U, dou
 }
 
 // Bilinear sample of the padded bitmap at (U', V') >= 0 (Supp. Eqs. S1-S3): M and its
-// derivatives along U' and V' on the floor cell. Forward and backward call this same code, so
-// both obtain bit-identical alpha (the backward's transmittance recovery relies on it).
+// derivatives along U' and V' on the floor cell. Forward and backward evaluate the same
+// arithmetic (blend_cell), so both obtain bit-identical alpha (the backward's transmittance
+// recovery relies on it).
 template <typename TexT>
-__device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex, int Wp, double U,
-                                         double V, float &M, float &MU, float &MV)
+__device__ __forceinline__ void blend_cell(const TexT *__restrict__ t, int Wp, float wu, float wv,
+                                           float &M, float &MU, float &MV)
 {
-    const float wu = (float)__builtin_amdgcn_fract(U), wv = (float)__builtin_amdgcn_fract(V);
-    const int iu = (int)U, iv = (int)V;
-    const TexT *t = atlas + (tex + iv * Wp + iu);
     const float p00 = texel<TexT>(t[0]), p01 = texel<TexT>(t[1]);
     const float p10 = texel<TexT>(t[Wp]), p11 = texel<TexT>(t[Wp + 1]);
     const float d0 = p01 - p00, d1 = p11 - p10;
@@ -129,6 +127,28 @@ __device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex
     MV = bot - top;
     M = fmaf(wv, MV, top);
     MU = fmaf(wv, d1 - d0, d0);
+}
+
+template <typename TexT>
+__device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex, int Wp, double U,
+                                         double V, float &M, float &MU, float &MV)
+{
+    const float wu = (float)__builtin_amdgcn_fract(U), wv = (float)__builtin_amdgcn_fract(V);
+    blend_cell<TexT>(atlas + (tex + (int)V * Wp + (int)U), Wp, wu, wv, M, MU, MV);
+}
+
+// The same for every lane of the wave: a lane outside the support samples the padded bitmap's
+// corner cell (0, 0) with zero weights, which reads only the zero border, so M = MU = MV = 0
+// there exactly (and alpha = 0: the lane's compositing state passes through unchanged).
+template <typename TexT>
+__device__ __forceinline__ void bilinear_all(const TexT *__restrict__ atlas, int tex, int Wp,
+                                             double U, double V, bool in, float &M, float &MU,
+                                             float &MV)
+{
+    const float wu = in ? (float)__builtin_amdgcn_fract(U) : 0.f;
+    const float wv = in ? (float)__builtin_amdgcn_fract(V) : 0.f;
+    const int off = in ? (int)V * Wp + (int)U : 0;
+    blend_cell<TexT>(atlas + (tex + off), Wp, wu, wv, M, MU, MV);
 }
 
 template <int TS>
@@ -156,6 +176,60 @@ __device__ __forceinline__ void bitonic_sort(int n, Get get, Set set, Sync sync)
             sync();
         }
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Wave reduction of 8 values per lane.
+// ------------------------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Transposed butterfly: v_permlane32_swap leaves values 0-3 summed over lanes l and l^32 in the
+// low half and values 4-7 in the high half; v_permlane16_swap halves again across rows; a
+// row_mirror step (with a select) across the two 8-lane halves of a row; then row_half_mirror,
+// quad_perm [1,0,3,2] and [2,3,0,1] add within groups of 8. On return lane l holds the wave
+// total of value (l >> 3). 18 VALU instructions, no LDS.
+__device__ __forceinline__ float reduce8(const float (&v)[8], int lane)
+{
+    float w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                        __float_as_uint(v[i + 4]), false, false);
+        w[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float x[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[i]),
+                                                        __float_as_uint(w[i + 2]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool h3 = lane & 8;
+    float y = (h3 ? x[1] : x[0]) + dpp<0x140>(h3 ? x[0] : x[1]);  // row_mirror
+    y += dpp<0x141>(y);                                            // row_half_mirror
+    y += dpp<0xB1>(y);                                             // quad_perm [1,0,3,2]
+    y += dpp<0x4E>(y);                                             // quad_perm [2,3,0,1]
+    return y;
+}
+
+// Sum of one value over the wave (result valid in every lane).
+__device__ __forceinline__ float wave_sum(float y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false,
+                                                    false);
+    y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false,
+                                                    false);
+    y = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    y += dpp<0x140>(y);
+    y += dpp<0x141>(y);
+    y += dpp<0xB1>(y);
+    y += dpp<0x4E>(y);
+    return y;
 }
 
 // Runs `body(tile)` for the tiles this workgroup owns under the launch schedule (see SCHED_*).
@@ -202,7 +276,11 @@ __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__r
     }
 }
 
-template <int TS, typename TexT, bool BG_PP>
+// FUSED: the forward of a fit step, followed in the same workgroup by the backward of the MSE
+// loss against `target` (the image, the per-pixel (K, T_K) and, for a list of at most 64
+// entries, the staged records are still on chip); the gradient is added to dparams and the
+// tile's squared error written to loss_tile.
+template <int TS, typename TexT, bool BG_PP, bool FUSED>
 __global__ void __launch_bounds__(TS * TS)
 k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
              int *__restrict__ tile_count, int *__restrict__ tile_len, int *__restrict__ list_max,
@@ -211,11 +289,14 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
              float *__restrict__ saveT, const int *__restrict__ flags,
              unsigned long long *__restrict__ pair_counter, int sched, int grab,
-             const int *__restrict__ order, int *__restrict__ queue)
+             const int *__restrict__ order, int *__restrict__ queue,
+             const float *__restrict__ target, float *__restrict__ loss_tile,
+             float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
     __shared__ __attribute__((aligned(16))) int s_ids[CAP + 4];
     __shared__ PrimRec s_rec[BATCH];
+    __shared__ float s_loss[TS * TS / 64];
     auto tile_body = [&](const int tile) {
         const int n = tile_count[tile];
         __syncthreads();  // every lane has read the count before it is re-armed
@@ -300,80 +381,139 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         atomicAdd(pair_counter + ((blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) &
                                   (DBMP_COUNTER_SLOTS - 1)),
                   npairs);
-    if (!tg.valid) return;
     const ImgDev &D = tg.D;
     const size_t plane = (size_t)D.H * D.W;
-    float b0, b1, b2;
-    if (BG_PP) {
-        const float *bp = bg + 3 * D.pix_off + tg.pix;
-        b0 = bp[0]; b1 = bp[plane]; b2 = bp[2 * plane];
-    } else {
-        b0 = bg[3 * tg.b]; b1 = bg[3 * tg.b + 1]; b2 = bg[3 * tg.b + 2];
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    if (tg.valid) {
+        if (BG_PP) {
+            const float *bp = bg + 3 * D.pix_off + tg.pix;
+            b0 = bp[0]; b1 = bp[plane]; b2 = bp[2 * plane];
+        } else {
+            b0 = bg[3 * tg.b]; b1 = bg[3 * tg.b + 1]; b2 = bg[3 * tg.b + 2];
+        }
     }
-    float *ip = image + 3 * D.pix_off + tg.pix;
-    ip[0] = fmaf(T, b0, C0);
-    ip[plane] = fmaf(T, b1, C1);
-    ip[2 * plane] = fmaf(T, b2, C2);
+    const float I0 = fmaf(T, b0, C0), I1 = fmaf(T, b1, C1), I2 = fmaf(T, b2, C2);
     const long long gp = D.pix_off + tg.pix;
-    if (alpha) alpha[gp] = 1.f - T;
-    saveK[gp] = K;
-    saveT[gp] = TK;
+    if (tg.valid) {
+        float *ip = image + 3 * D.pix_off + tg.pix;
+        ip[0] = I0;
+        ip[plane] = I1;
+        ip[2 * plane] = I2;
+        if (alpha) alpha[gp] = 1.f - T;
+        saveK[gp] = K;
+        saveT[gp] = TK;
+    }
+    if constexpr (FUSED) {
+        // dL/dI of the image's MSE, formed as the separate MSE backward forms it
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, sq = 0.f;
+        if (tg.valid) {
+            const float *tp = target + 3 * D.pix_off + tg.pix;
+            const float e0 = I0 - tp[0], e1 = I1 - tp[plane], e2 = I2 - tp[2 * plane];
+            sq = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+            const float sc = 2.f / (3.f * (float)plane);
+            g0 = sc * e0; g1 = sc * e1; g2 = sc * e2;
+        }
+        const int lane = threadIdx.x & 63;
+        const bool staged = n <= BATCH;  // the forward's only batch is still in s_rec
+        if (in_lds)
+            bwd_walk<NT, TexT, false>(n, [&](int j) { return s_ids[j]; }, staged, s_rec, recs,
+                                      atlas, Wp, tg, vmask, g0, g1, g2, 0.f, b0, b1, b2,
+                                      tg.valid ? K : -1, TK, dparams, cu1, cv1, cu_cv, cv_cu,
+                                      lane);
+        else
+            bwd_walk<NT, TexT, false>(n, [&](int j) { return ((volatile int *)seg)[j]; },
+                                      staged, s_rec, recs, atlas, Wp, tg, vmask, g0, g1, g2,
+                                      0.f, b0, b1, b2, tg.valid ? K : -1, TK, dparams, cu1, cv1,
+                                      cu_cv, cv_cu, lane);
+        const float ws = wave_sum(sq);
+        if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int w = 0; w < TS * TS / 64; ++w) t += s_loss[w];
+            loss_tile[tile] = t;
+        }
+    }
     };
     run_schedule(sched, grab, order, queue, n_tiles, tile_body);
 }
 
-// ------------------------------------------------------------------------------------------
-// Wave reduction of 8 values per lane.
-// ------------------------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v)
+// The backward's walk over a tile's sorted list (entry j's id is id_at(j)), back to front in
+// batches of 64 entries (Supp. Eqs. S4-S5, Eq. 7): per pixel, g = dL/dI, ga = dL/dA, G = the
+// background, and the forward's (K, T_K). `staged`: the whole list (n <= 64) is already in
+// s_rec, staged by the forward of the fused step.
+template <int NT, typename TexT, bool HAS_GA, int TS, typename IdAt>
+__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
+                                         PrimRec *__restrict__ s_rec,
+                                         const PrimRec *__restrict__ recs,
+                                         const TexT *__restrict__ atlas, int Wp,
+                                         const TileGeom<TS> &tg, uint64_t vmask, float g0,
+                                         float g1, float g2, float ga, float G0, float G1,
+                                         float G2, int K, float TK, float *__restrict__ dparams,
+                                         double cu1, double cv1, float cu_cv, float cv_cu,
+                                         int lane)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-// Transposed butterfly: v_permlane32_swap leaves values 0-3 summed over lanes l and l^32 in the
-// low half and values 4-7 in the high half; v_permlane16_swap halves again across rows; a
-// row_mirror step (with a select) across the two 8-lane halves of a row; then row_half_mirror,
-// quad_perm [1,0,3,2] and [2,3,0,1] add within groups of 8. On return lane l holds the wave
-// total of value (l >> 3). 18 VALU instructions, no LDS.
-__device__ __forceinline__ float reduce8(const float (&v)[8], int lane)
-{
-    float w[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
-                                                        __float_as_uint(v[i + 4]), false, false);
-        w[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const double xd = tg.px, yd = tg.py;
+    float Bk = 1.f, Trun = TK;
+    for (int hi = n; hi > 0; hi -= BATCH) {
+        const int b0 = max(0, hi - BATCH), cnt = hi - b0;
+        if (!(staged && b0 == 0)) {
+            __syncthreads();  // the previous batch is consumed
+            stage_batch<NT>(s_rec, recs, b0, cnt, id_at);
+            __syncthreads();
+        }
+        uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
+        while (hits) {  // descending list order: back to front
+            const int e = 63 - __builtin_clzll(hits);
+            hits ^= 1ull << e;
+            const PrimRec &r = s_rec[e];
+            const int j = b0 + e;
+            const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+            const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+            const uint64_t msk = support_mask(r, U, V, vmask);
+            if (msk == 0) continue;
+            // every lane runs the update; outside the support alpha = M = dM = 0, so its
+            // partials are zero and its state (T, G, B) passes through unchanged (no branch
+            // and no zeroing: the vector instructions issue for the whole wave either way)
+            float d[8];
+            float M, MU, MV;
+            bilinear_all<TexT>(atlas, r.tex, Wp, U, V,
+                               __builtin_amdgcn_inverse_ballot_w64(msk), M, MU, MV);
+            const float a = r.ka * M;
+            const float m = 1.f - a;
+            // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp;
+            // exactly 1 where alpha = 0)
+            float rc = __builtin_amdgcn_rcpf(m);
+            rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
+            const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
+            Trun = Tj;
+            const float cr = r.cr, cg = r.cg, cb = r.cb;
+            float dal = g0 * (cr - G0);
+            dal = fmaf(g1, cg - G1, dal);
+            dal = fmaf(g2, cb - G2, dal);
+            if (HAS_GA) dal = fmaf(ga, Bk, dal);
+            dal *= Tj;
+            const float ta = Tj * a;
+            d[5] = g0 * ta * r.ccr;
+            d[6] = g1 * ta * r.ccg;
+            d[7] = g2 * ta * r.ccb;
+            d[4] = dal * r.kaom * M;
+            const float dM = dal * r.ka;
+            const float gU = dM * MU, gV = dM * MV;
+            const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
+            // negated operands (free source modifiers) rather than negated results
+            d[0] = fmaf(-gU, r.faU, -(gV * r.faV));
+            d[1] = fmaf(-gU, r.fbU, -(gV * r.fbV));
+            d[2] = fmaf(-gU, Ub, -(gV * Vb));
+            d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
+            G0 = fmaf(m, G0, a * cr);
+            G1 = fmaf(m, G1, a * cg);
+            G2 = fmaf(m, G2, a * cb);
+            Bk *= m;
+            const float tot = reduce8(d, lane);
+            if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
+        }
     }
-    float x[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[i]),
-                                                        __float_as_uint(w[i + 2]), false, false);
-        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-    const bool h3 = lane & 8;
-    float y = (h3 ? x[1] : x[0]) + dpp<0x140>(h3 ? x[0] : x[1]);  // row_mirror
-    y += dpp<0x141>(y);                                            // row_half_mirror
-    y += dpp<0xB1>(y);                                             // quad_perm [1,0,3,2]
-    y += dpp<0x4E>(y);                                             // quad_perm [2,3,0,1]
-    return y;
-}
-
-// Sum of one value over the wave (result valid in every lane).
-__device__ __forceinline__ float wave_sum(float y)
-{
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false,
-                                                    false);
-    y = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false,
-                                                    false);
-    y = __uint_as_float(q[0]) + __uint_as_float(q[1]);
-    y += dpp<0x140>(y);
-    y += dpp<0x141>(y);
-    y += dpp<0xB1>(y);
-    y += dpp<0x4E>(y);
-    return y;
 }
 
 // MSE: the backward forms dL/dI = scale (I - target) itself from the forward's image and writes
@@ -426,64 +566,10 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             K = saveK[gp];
             TK = saveT[gp];
         }
-        float Bk = 1.f, Trun = TK;
         const int *seg = lists + (size_t)tile * list_cap;
-        for (int hi = n; hi > 0; hi -= BATCH) {
-            const int b0 = max(0, hi - BATCH), cnt = hi - b0;
-            __syncthreads();  // the previous batch is consumed
-            stage_batch<TS * TS>(s_rec, recs, b0, cnt, [&](int j) { return seg[j]; });
-            __syncthreads();
-            uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
-            while (hits) {  // descending list order: back to front
-                const int e = 63 - __builtin_clzll(hits);
-                hits ^= 1ull << e;
-                const PrimRec &r = s_rec[e];
-                const int j = b0 + e;
-                const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
-                const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-                const uint64_t msk = support_mask(r, U, V, vmask);
-                if (msk == 0) continue;
-                float d[8];
-    #pragma unroll
-                for (int q = 0; q < 8; ++q) d[q] = 0.f;
-                if (__builtin_amdgcn_inverse_ballot_w64(msk)) {
-                    float M, MU, MV;
-                    bilinear<TexT>(atlas, r.tex, Wp, U, V, M, MU, MV);
-                    const float a = r.ka * M;
-                    const float m = 1.f - a;
-                    // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp)
-                    float rc = __builtin_amdgcn_rcpf(m);
-                    rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
-                    const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
-                    Trun = Tj;
-                    const float cr = r.cr, cg = r.cg, cb = r.cb;
-                    float dal = g0 * (cr - G0);
-                    dal = fmaf(g1, cg - G1, dal);
-                    dal = fmaf(g2, cb - G2, dal);
-                    if (HAS_GA) dal = fmaf(ga, Bk, dal);
-                    dal *= Tj;
-                    const float ta = Tj * a;
-                    d[5] = g0 * ta * r.ccr;
-                    d[6] = g1 * ta * r.ccg;
-                    d[7] = g2 * ta * r.ccb;
-                    d[4] = dal * r.kaom * M;
-                    const float dM = dal * r.ka;
-                    const float gU = dM * MU, gV = dM * MV;
-                    const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
-                    // negated operands (free source modifiers) rather than negated results
-                    d[0] = fmaf(-gU, r.faU, -(gV * r.faV));
-                    d[1] = fmaf(-gU, r.fbU, -(gV * r.fbV));
-                    d[2] = fmaf(-gU, Ub, -(gV * Vb));
-                    d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
-                    G0 = fmaf(m, G0, a * cr);
-                    G1 = fmaf(m, G1, a * cg);
-                    G2 = fmaf(m, G2, a * cb);
-                    Bk *= m;
-                }
-                const float tot = reduce8(d, lane);
-                if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
-            }
-        }
+        bwd_walk<TS * TS, TexT, HAS_GA>(n, [&](int j) { return seg[j]; }, false, s_rec, recs,
+                                        atlas, Wp, tg, vmask, g0, g1, g2, ga, G0, G1, G2, K, TK,
+                                        dparams, cu1, cv1, cu_cv, cv_cu, lane);
         if (MSE) {
             const float ws = wave_sum(sq);
             if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
@@ -538,15 +624,17 @@ static void launch(K kern, int grid, int block, hipStream_t st, hipEvent_t e0, h
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, args...);
 }
 
-template <int TS, typename TexT, bool BGPP>
+template <int TS, typename TexT, bool BGPP, bool FUSED>
 static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
+    const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
     const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
-    launch(k_raster_fwd<TS, TexT, BGPP>, grid, TS * TS, st, a.ev_start, a.ev_stop,
+    launch(k_raster_fwd<TS, TexT, BGPP, FUSED>, grid, TS * TS, st, a.ev_start, a.ev_stop,
         a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len, a.list_max,
         a.imgs,
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
-        a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue);
+        a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue, a.target,
+        a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu));
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA, bool MSE>
@@ -564,7 +652,11 @@ static void bwd_t(const RasterArgs &a, hipStream_t st)
 template <int TS, typename TexT>
 static void fwd_d1(const RasterArgs &a, hipStream_t st)
 {
-    if (a.bg_pp) fwd_t<TS, TexT, true>(a, st); else fwd_t<TS, TexT, false>(a, st);
+    if (a.target) {
+        if (a.bg_pp) fwd_t<TS, TexT, true, true>(a, st); else fwd_t<TS, TexT, false, true>(a, st);
+    } else {
+        if (a.bg_pp) fwd_t<TS, TexT, true, false>(a, st); else fwd_t<TS, TexT, false, false>(a, st);
+    }
 }
 template <int TS>
 static void fwd_d0(const RasterArgs &a, hipStream_t st)
@@ -618,6 +710,12 @@ hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st)
         default: bwd_d0<32>(a, st); break;
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill0(float *p, long long n, hipStream_t st)
+{
+    if (n > 0) k_fill0<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ from .render import Renderer
 class Fitter:
     def __init__(self, params, atlas_idx, atlas, target, bg=None, alpha_max=1.0, tile=16,
                  lr=1e-2, betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0,
-                 accumulate=True):
+                 accumulate=True, fused=True):
         dev = params.device
         self.H, self.W = int(target.shape[1]), int(target.shape[2])
         self.params = params.detach().clone().contiguous()
@@ -38,6 +38,7 @@ class Fitter:
         self.R = renderer if renderer is not None else Renderer(device=dev.index, check=False)
         self.headroom = headroom
         self.accumulate = accumulate  # backward adds into grad, Adam zeroes it (no clear kernel)
+        self.fused = fused  # forward and MSE backward in one launch (dbmp_render_mse)
         self.graph = None
         self._sized = False
 
@@ -48,10 +49,18 @@ class Fitter:
         self.R.render(self.params, self.atlas_idx, None, self.H, self.W, self.bg,
                       self.alpha_max, self.tile, image=self.image, with_alpha=False)
 
+    def _render_mse(self):
+        self.R.render_mse(self.params, self.atlas_idx, None, self.H, self.W, self.target,
+                          self.bg, self.alpha_max, self.tile, image=self.image, out=self.grad,
+                          accumulate=self.accumulate)
+
     def _enqueue(self):
         st = capi.stream_handle()
-        self._render()
-        self.R.backward_mse(self.target, None, out=self.grad, accumulate=self.accumulate)
+        if self.fused:
+            self._render_mse()
+        else:
+            self._render()
+            self.R.backward_mse(self.target, None, out=self.grad, accumulate=self.accumulate)
         capi.dbmp_adam_step(st, self.params, self.grad, self.m, self.v, self.params.numel(),
                             self.lr, self.betas[0], self.betas[1], self.eps, self.step_count,
                             zero_grad=1 if self.accumulate else 0)
@@ -184,7 +193,7 @@ class BatchFitter(Fitter):
     (white)."""
 
     def __init__(self, fits, atlas, bg=None, alpha_max=1.0, tile=16, lr=1e-2,
-                 betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0):
+                 betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0, fused=True):
         dev = fits[0][0].device
         self.descs = []
         prim, pix = 0, 0
@@ -211,12 +220,18 @@ class BatchFitter(Fitter):
         self.R = renderer if renderer is not None else Renderer(device=dev.index, check=False)
         self.headroom = headroom
         self.accumulate = True
+        self.fused = fused
         self.graph = None
         self._sized = False
 
     def _render(self):
         self.R.render_batched(self.descs, self.params, self.atlas_idx, None, self.bg,
                               self.alpha_max, self.tile, image=self.image, with_alpha=False)
+
+    def _render_mse(self):
+        self.R.render_batched_mse(self.descs, self.params, self.atlas_idx, None, self.bg,
+                                  self.target, self.alpha_max, self.tile, image=self.image,
+                                  out=self.grad, accumulate=True)
 
     def shapes(self):
         return [(h, w, n) for (h, w, n, _, _) in self.descs]

@@ -100,3 +100,10 @@ def bwd_algorithmic_bytes(H, W, N, atlas_bytes):
     gradients out (32 B each) and the atlas once. Tile list ids (4 B per tile-primitive pair,
     under 2 % of the total at these workloads) are not counted."""
     return 32 * H * W + 64 * N + atlas_bytes
+
+
+def fused_algorithmic_bytes(H, W, N, atlas_bytes):
+    """HBM bytes of the fused fit step (forward + MSE backward in one launch): the target in,
+    the image and the per-pixel (K, T_K) out (12 + 12 + 8 B per pixel), parameters in and
+    gradients out (32 + 32 B per primitive) and the atlas once; tile list ids not counted."""
+    return 32 * H * W + 64 * N + atlas_bytes

@@ -42,6 +42,10 @@ class Renderer:
         self.ctx = capi.dbmp_create(dev.index, list_capacity)
         self.check_each = check
         self.generation = 0
+        # device buffers the context's saved forward state points to (the backward reads the
+        # image and the background): held until the next forward so they cannot be freed and
+        # reused while a backward may still read them
+        self._fwd_buffers = ()
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -103,6 +107,7 @@ class Renderer:
         st = capi.stream_handle()
         args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, dcode, H, W,
                 bg, bg_pp, alpha_max, tile, image, alpha)
+        self._fwd_buffers = (image, alpha, bg)
         capi.dbmp_render(*args)
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
@@ -140,6 +145,7 @@ class Renderer:
         st = capi.stream_handle()
         args = (self.ctx, st, cd, params, atlas_idx, atlas, B, Hb, Wb, dcode, bg,
                 alpha_max, tile, image, alpha)
+        self._fwd_buffers = (image, alpha, bg)
         capi.dbmp_render_batched(*args)
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
@@ -152,6 +158,79 @@ class Renderer:
                 raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
         self.generation += 1
         return image, alpha
+
+    # -- fused fit step: forward + MSE backward ----------------------------------------------
+    def render_mse(self, params, atlas_idx, atlas, H, W, target, bg=None, alpha_max=1.0,
+                   tile=16, image=None, out=None, accumulate=False):
+        """Forward and the MSE backward in one launch per stage (dbmp_render_mse): returns
+        (image, dL/dparams). With check=True an overflowing list is grown and the step redone
+        when the gradient is overwritten; an accumulating caller gets the error and restores its
+        own state (Fitter.run does)."""
+        _need(params, "params", torch.float32)
+        N = params.shape[0]
+        _need(atlas_idx, "atlas_idx", torch.int32, (N,))
+        _need(target, "target", torch.float32, (3, H, W))
+        if atlas is None:
+            B = Hb = Wb = 0
+            dcode = 0
+        else:
+            if atlas.dim() == 2:
+                atlas = atlas[None]
+            _need(atlas, "atlas")
+            B, Hb, Wb = atlas.shape
+            dcode = _dtype_code(atlas)
+        if bg is None:
+            bg = torch.ones(3, device=params.device, dtype=torch.float32)
+        _need(bg, "bg", torch.float32)
+        bg_pp = 0 if bg.numel() == 3 else 1
+        if image is None:
+            image = torch.empty(3, H, W, device=params.device, dtype=torch.float32)
+        if out is None:
+            out = torch.zeros(N, 8, device=params.device, dtype=torch.float32)
+        st = capi.stream_handle()
+        args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, dcode, H, W, bg, bg_pp,
+                alpha_max, tile, target, image, out, 1 if accumulate else 0)
+        self._fwd_buffers = (image, bg)
+        capi.dbmp_render_mse(*args)
+        if self.check_each:
+            rc = capi.dbmp_check(self.ctx, st)
+            if rc == capi.DBMP_EOVERFLOW and not accumulate:
+                need = capi.dbmp_longest_list(self.ctx, st)
+                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 16)
+                capi.dbmp_render_mse(*args)
+                rc = capi.dbmp_check(self.ctx, st)
+            if rc != capi.DBMP_OK:
+                raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
+        self.generation += 1
+        return image, out
+
+    def render_batched_mse(self, descs, params, atlas_idx, atlas, bg, target, alpha_max=1.0,
+                           tile=16, image=None, out=None, accumulate=False):
+        """dbmp_render_batched_mse; target laid out like the batched image."""
+        _need(params, "params", torch.float32)
+        _need(atlas_idx, "atlas_idx", torch.int32)
+        _need(bg, "bg", torch.float32, (len(descs), 3))
+        _need(target, "target", torch.float32)
+        if atlas is None:
+            B = Hb = Wb = 0
+            dcode = 0
+        else:
+            _need(atlas, "atlas")
+            B, Hb, Wb = atlas.shape
+            dcode = _dtype_code(atlas)
+        npix = max(int(d[4]) + int(d[0]) * int(d[1]) for d in descs)
+        if image is None:
+            image = torch.empty(3 * npix, device=params.device, dtype=torch.float32)
+        if out is None:
+            out = torch.zeros(params.shape[0], 8, device=params.device, dtype=torch.float32)
+        cd = [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))
+              for (h, w, n, po, xo) in descs]
+        self._fwd_buffers = (image, bg)
+        capi.dbmp_render_batched_mse(self.ctx, capi.stream_handle(), cd, params, atlas_idx, atlas,
+                                     B, Hb, Wb, dcode, bg, alpha_max, tile, target, image, out,
+                                     1 if accumulate else 0)
+        self.generation += 1
+        return image, out
 
     # -- backward ----------------------------------------------------------------------------
     def backward(self, dL_dimage, dL_dalpha=None, n_params=None, out=None):

@@ -20,7 +20,8 @@ def test_header_declares_the_boundary():
               "dbmp_render_batched", "dbmp_check", "dbmp_last_error", "dbmp_mse_grad",
               "dbmp_adam_step", "dbmp_reserve", "dbmp_longest_list",
               "dbmp_render_backward_mse", "dbmp_mse_loss", "dbmp_support_pairs",
-              "dbmp_set_atlas"]:
+              "dbmp_set_atlas", "dbmp_render_mse", "dbmp_render_batched_mse",
+              "dbmp_set_schedule", "dbmp_time_next_launch"]:
         assert n in names
 
 
@@ -78,5 +79,9 @@ def test_host_argument_checks_need_no_device():
     assert lib.dbmp_longest_list(None, None) == -1
     assert lib.dbmp_set_schedule(None, 1, 4, 1) == capi.DBMP_EINVAL
     assert lib.dbmp_time_next_launch(None, 1, None, None) == capi.DBMP_EINVAL
+    assert lib.dbmp_render_mse(None, None, None, None, 0, None, 1, 2, 2, 0, 4, 4, None, 0, 1.0,
+                               16, None, None, None, 0) == capi.DBMP_EINVAL
+    assert lib.dbmp_render_batched_mse(None, None, 1, None, None, None, None, 1, 2, 2, 0, None,
+                                       1.0, 16, None, None, None, 0) == capi.DBMP_EINVAL
     h = ctypes.c_void_p()
     assert lib.dbmp_create(ctypes.byref(h), 0, -5) == capi.DBMP_EINVAL

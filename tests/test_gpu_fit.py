@@ -279,3 +279,106 @@ def test_time_next_launch_records_kernel_duration():
     assert 0 < kf < wall and 0 < kb < wall and kf + kb < wall, (kf, kb, wall)
     with pytest.raises(capi.DbmpError):
         capi.dbmp_time_next_launch(R.ctx, 2, None, None)
+
+
+# ------------------------------------------------------------------------------------------
+# Fused fit step: forward + MSE backward in one launch per stage
+# ------------------------------------------------------------------------------------------
+def _fused_vs_separate(R1, R2, p, idx, a, H, W, t, tile):
+    img1, _ = R1.render(p, idx, a, H, W, None, 1.0, tile)
+    g1 = R1.backward_mse(t, None, n_params=p.shape[0])
+    l1 = torch.zeros(1, device="cuda")
+    R1.mse_loss(l1)
+    img2, g2 = R2.render_mse(p, idx, a, H, W, t, None, 1.0, tile)
+    l2 = torch.zeros(1, device="cuda")
+    R2.mse_loss(l2)
+    R1.check()
+    R2.check()
+    assert torch.equal(img1, img2)
+    g1, g2 = g1.cpu().numpy().astype(np.float64), g2.cpu().numpy().astype(np.float64)
+    scale = np.abs(g1).max(axis=0) + 1e-30  # per column: fp32 atomics in another order
+    assert np.all(np.abs(g1 - g2) <= 1e-5 * scale), np.max(np.abs(g1 - g2) / scale)
+    assert abs(l1.item() - l2.item()) <= 1e-6 * l1.item()
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_fused_step_equals_separate_calls(tile):
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c1")
+    p = torch.tensor(d["params"], device="cuda")
+    idx = torch.tensor(d["idx"], device="cuda")
+    a = torch.tensor(d["atlas"], device="cuda")
+    t = torch.tensor(d["target"], device="cuda")
+    _fused_vs_separate(Renderer(), Renderer(), p, idx, a, 512, 512, t, tile)
+
+
+def test_fused_step_long_lists_and_accumulate():
+    """Lists longer than one staged batch (64 entries) and longer than the LDS sort buffer, and
+    the accumulate flag."""
+    from paper_2602_22625_amd.render import Renderer
+    g = np.random.default_rng(21)
+    H = W = 96
+    N = 5000
+    p, idx = synth.init_params(N, H, W, math.log(40.0), 0.2, 16, 22)
+    a = torch.tensor(synth.make_atlas("ss64x16"), device="cuda")
+    P = torch.tensor(p, device="cuda")
+    I = torch.tensor(idx, device="cuda")
+    T = torch.tensor(g.uniform(0, 1, (3, H, W)).astype(np.float32), device="cuda")
+    R1, R2 = Renderer(), Renderer()
+    _fused_vs_separate(R1, R2, P, I, a, H, W, T, 16)
+    assert R2.longest_list() > 2048
+    base = 1e-3  # small: the atomics add each partial into it with its own rounding
+    out = torch.full((N, 8), base, device="cuda")
+    _, g = R2.render_mse(P, I, a, H, W, T, None, 1.0, 16, out=out, accumulate=True)  # sized
+    ref = R1.backward_mse(T, None, n_params=N)
+    R2.check()
+    d = (g - base - ref).abs().cpu().numpy()
+    scale = ref.abs().cpu().numpy().max(axis=0) + 1e-30  # per column, as above
+    assert np.all(d <= 1e-5 * scale), np.max(d / scale)
+
+
+def test_fused_batched_step_equals_separate_calls():
+    from paper_2602_22625_amd.render import Renderer
+    atlas = torch.tensor(synth.make_atlas("ss64x16"), device="cuda")
+    descs, ps, ids, tg, po, xo = [], [], [], [], 0, 0
+    for k, (H, W, N) in enumerate([(72, 56, 120), (40, 104, 60), (16, 16, 0), (88, 64, 200)]):
+        pr, ix = synth.init_params(N, H, W, math.log(9.0), 0.5, 16, 700 + k)
+        descs.append((H, W, N, po, xo))
+        ps.append(pr); ids.append(ix)
+        tg.append(synth.target_image(H, W, 4, 800 + k).reshape(-1))
+        po += N
+        xo += H * W
+    P = torch.tensor(np.concatenate(ps), device="cuda")
+    I = torch.tensor(np.concatenate(ids), device="cuda")
+    T = torch.tensor(np.concatenate(tg), device="cuda")
+    bg = torch.ones(len(descs), 3, device="cuda")
+    R1, R2 = Renderer(), Renderer()
+    img1, _ = R1.render_batched(descs, P, I, atlas, bg, 1.0, 16)
+    g1 = R1.backward_mse(T, None, n_params=po)
+    img2, g2 = R2.render_batched_mse(descs, P, I, atlas, bg, T, 1.0, 16)
+    l1, l2 = torch.zeros(4, device="cuda"), torch.zeros(4, device="cuda")
+    R1.mse_loss(l1)
+    R2.mse_loss(l2)
+    R1.check()
+    R2.check()
+    assert torch.equal(img1, img2)
+    assert torch.allclose(g1, g2, rtol=1e-5, atol=1e-9)
+    assert torch.allclose(l1, l2, rtol=1e-6)
+
+
+def test_fitter_fused_matches_unfused():
+    from paper_2602_22625_amd.fit import Fitter
+    d = synth.make_workload("c0")
+    p = torch.tensor(d["params"], device="cuda")
+    idx = torch.tensor(d["idx"], device="cuda")
+    a = torch.tensor(d["atlas"], device="cuda")
+    t = torch.tensor(d["target"], device="cuda")
+    f1 = Fitter(p, idx, a, t, fused=False)
+    f2 = Fitter(p, idx, a, t, fused=True)
+    f2.capture()
+    for _ in range(5):
+        f1.step()
+        f2.step()
+        assert abs(f1.loss() - f2.loss()) <= 1e-4 * f1.loss()
+    f1.check()
+    f2.check()

@@ -478,3 +478,25 @@ def test_c2_autograd_matches_finite_differences_on_32_parameters():
     print("FD relative errors per column:",
           [np.round(rel[4 * q:4 * q + 4], 5).tolist() for q in range(8)])
     assert np.all(rel < 1e-2), list(zip(picks, an, fd, rel))
+
+
+def test_backward_after_the_caller_dropped_the_forward_outputs():
+    """The MSE backward reads the forward's image and background. A caller that drops the
+    returned image (and passed no background, so the Renderer made one) must still get the
+    right gradient: the Renderer keeps those buffers alive until the next forward. New
+    allocations filled with NaN would take the memory of freed buffers."""
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c0")
+    p, idx, a = to_dev(d)
+    t = torch.tensor(d["target"], device="cuda")
+    R2 = Renderer()
+    R2.render(p, idx, a, 128, 128)  # outputs dropped
+    junk = [torch.full((3, 128, 128), float("nan"), device="cuda") for _ in range(8)]
+    junk += [torch.full((3,), float("nan"), device="cuda") for _ in range(8)]
+    g = R2.backward_mse(t, None, n_params=p.shape[0])
+    R2.check()
+    ref, _ = oracle.render(d["params"], d["idx"], d["atlas"], 128, 128)
+    _, gI = oracle.mse(ref, d["target"])
+    gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], 128, 128, gI)
+    assert_grads(g.cpu().numpy(), gref)
+    del junk
