@@ -76,8 +76,11 @@ int dbmp_reserve(dbmp_ctx *ctx, long long list_capacity);
  * forwards). Results do not depend on it: every tile is computed the same way; only which
  * workgroup computes it, and when, changes.
  *   DBMP_SCHED_GRID        one workgroup per screen tile, in image order (default).
- *   DBMP_SCHED_SORTED      one workgroup per tile, tiles dealt longest list first (a counting
- *                          sort of the tile list lengths runs after binning).
+ *   DBMP_SCHED_SORTED      one workgroup per tile, tiles dealt longest list first: by the list
+ *                          lengths of the previous forward on this context (an extra binning
+ *                          workgroup sorts them while the others bin; up to 4,096 tiles), or of
+ *                          this forward (a counting sort after binning; more tiles). Any order is
+ *                          valid: it only balances the compute units.
  *   DBMP_SCHED_PERSISTENT  workgroups_per_cu x (compute units) workgroups stay resident and take
  *                          tiles, longest list first: items_per_grab tiles at a time from a
  *                          device work queue until it is empty, or, with items_per_grab = 0,

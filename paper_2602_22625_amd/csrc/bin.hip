@@ -108,6 +108,88 @@ __device__ __forceinline__ bool tile_hits(const R &r, int X0, int X1, int Y0, in
 }
 
 // ------------------------------------------------------------------------------------------
+// Tiles by decreasing list length, for the sorted and persistent schedules: a histogram of the
+// lengths (capped at ORDER_BINS - 1) in LDS, an exclusive scan of the bins from the longest
+// down, then a scatter. Ties are placed in any order: every tile is computed independently, so
+// the order changes no image bit. Run by NTH threads of one workgroup: by an extra workgroup of
+// k_prep on the previous forward's lengths (small canvases: no launch of its own, and off the
+// critical path), else by k_order after the binning.
+// ------------------------------------------------------------------------------------------
+constexpr int ORDER_BINS = 1024;
+constexpr int ORDER_IN_PREP_MAX = 4096;  // tiles up to which the binning orders them
+constexpr int ORDER_KEEP = 16;           // tile lengths per thread read once and kept
+
+template <int NTH, bool ATOMIC_READS>
+__device__ __forceinline__ void order_tiles(const int *__restrict__ tile_count, int n_tiles,
+                                            int *__restrict__ order, int *hist, int *wsum)
+{
+    static_assert(ORDER_BINS % NTH == 0 && NTH % 64 == 0, "bins per thread");
+    constexpr int BPT = ORDER_BINS / NTH;  // consecutive bins owned by one thread
+    const int t = threadIdx.x;
+    // bin 0 holds the longest lists
+    auto bin = [](int len) { return ORDER_BINS - 1 - min(max(len, 0), ORDER_BINS - 1); };
+    auto count = [&](int i) {
+        // counts appended by other workgroups of the same launch are read at device scope
+        return ATOMIC_READS ? __hip_atomic_load(tile_count + i, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : tile_count[i];
+    };
+    // each thread's tiles' bins, read once (up to ORDER_KEEP per thread kept in registers)
+    constexpr int KEEP = ORDER_KEEP;
+    int kb[KEEP];
+#pragma unroll
+    for (int k = 0; k < KEEP; ++k) {
+        const int i = t + k * NTH;
+        kb[k] = i < n_tiles ? bin(count(i)) : 0;
+    }
+    for (int b = t; b < ORDER_BINS; b += NTH) hist[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KEEP; ++k)
+        if (t + k * NTH < n_tiles) atomicAdd(&hist[kb[k]], 1);
+    for (int i = t + KEEP * NTH; i < n_tiles; i += NTH) atomicAdd(&hist[bin(count(i))], 1);
+    __syncthreads();
+    // exclusive scan: within the thread's bins, then wave-inclusive scans of the thread sums,
+    // then the wave totals
+    int sum = 0;
+    for (int k = 0; k < BPT; ++k) {
+        const int v = hist[t * BPT + k];
+        hist[t * BPT + k] = sum;
+        sum += v;
+    }
+    int x = sum;
+    const int lane = t & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[t >> 6] = x;
+    __syncthreads();
+    int base = x - sum;
+    for (int w = 0; w < (t >> 6); ++w) base += wsum[w];
+    for (int k = 0; k < BPT; ++k) hist[t * BPT + k] += base;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KEEP; ++k) {
+        const int i = t + k * NTH;
+        if (i < n_tiles) order[atomicAdd(&hist[kb[k]], 1)] = i;
+    }
+    for (int i = t + KEEP * NTH; i < n_tiles; i += NTH) {
+        const int pos = atomicAdd(&hist[bin(count(i))], 1);
+        order[pos] = i;
+    }
+}
+
+__global__ void __launch_bounds__(ORDER_BINS)
+k_order(const int *__restrict__ tile_count, int n_tiles, int *__restrict__ order)
+{
+    __shared__ int hist[ORDER_BINS];
+    __shared__ int wsum[ORDER_BINS / 64];
+    order_tiles<ORDER_BINS, false>(tile_count, n_tiles, order, hist, wsum);
+}
+
+// ------------------------------------------------------------------------------------------
 // k_prep
 // ------------------------------------------------------------------------------------------
 #define PREP_THREADS 256
@@ -125,8 +207,17 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
        const ImgDev *__restrict__ imgs, int n_images, const int *__restrict__ box, int B, int Hb,
        int Wb, int Wp, float alpha_max, int TS, PrimRec *__restrict__ recs,
        int *__restrict__ tile_count, int *__restrict__ lists, int list_cap,
-       int *__restrict__ flags)
+       int *__restrict__ flags, int n_tiles, int *__restrict__ order,
+       const int *__restrict__ prev_len)
 {
+    if (order && blockIdx.x == gridDim.x - 1) {
+        // the extra workgroup: tiles by decreasing list length of the previous forward, while
+        // the others bin (any permutation is a valid order; a fit's lists change slowly)
+        __shared__ int hist[ORDER_BINS];
+        __shared__ int wsum[PREP_THREADS / 64];
+        order_tiles<PREP_THREADS, false>(prev_len, n_tiles, order, hist, wsum);
+        return;
+    }
     __shared__ WalkRec s_rec[PREP_PRIMS];
     if (threadIdx.x < PREP_PRIMS) {
         const long long g = (long long)blockIdx.x * PREP_PRIMS + threadIdx.x;
@@ -264,53 +355,6 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
 // ------------------------------------------------------------------------------------------
 // Host launcher
 // ------------------------------------------------------------------------------------------
-// ------------------------------------------------------------------------------------------
-// k_order: tiles by decreasing list length, for the sorted and persistent schedules. One
-// workgroup: a histogram of the lengths (capped at ORDER_BINS - 1) in LDS, an exclusive scan of
-// the bins from the longest down, then a scatter. Ties are placed in any order: every tile is
-// computed independently, so the order changes no image bit.
-// ------------------------------------------------------------------------------------------
-constexpr int ORDER_BINS = 1024;
-
-__global__ void __launch_bounds__(ORDER_BINS)
-k_order(const int *__restrict__ tile_count, int n_tiles, int *__restrict__ order)
-{
-    __shared__ int hist[ORDER_BINS];
-    __shared__ int wsum[ORDER_BINS / 64];
-    const int t = threadIdx.x;
-    hist[t] = 0;
-    __syncthreads();
-    // bin 0 holds the longest lists
-    auto bin = [](int len) { return ORDER_BINS - 1 - min(max(len, 0), ORDER_BINS - 1); };
-    for (int i = t; i < n_tiles; i += ORDER_BINS) atomicAdd(&hist[bin(tile_count[i])], 1);
-    __syncthreads();
-    // exclusive scan over the bins: wave-inclusive scans, then the wave totals
-    const int v = hist[t];
-    int x = v;
-    const int lane = t & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[t >> 6] = x;
-    __syncthreads();
-    int base = 0;
-    for (int w = 0; w < (t >> 6); ++w) base += wsum[w];
-    hist[t] = base + x - v;
-    __syncthreads();
-    for (int i = t; i < n_tiles; i += ORDER_BINS) {
-        const int pos = atomicAdd(&hist[bin(tile_count[i])], 1);
-        order[pos] = i;
-    }
-}
-
-hipError_t launch_order(const int *tile_count, int n_tiles, int *order, hipStream_t st)
-{
-    if (n_tiles > 0) k_order<<<1, ORDER_BINS, 0, st>>>(tile_count, n_tiles, order);
-    return hipGetLastError();
-}
-
 hipError_t launch_binning(const BinArgs &a, hipStream_t st)
 {
     if (a.pad_atlas) {
@@ -322,10 +366,17 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
                                                               a.Wb, (uint16_t *)a.atlas_pad, a.Wp,
                                                               a.box);
     }
-    if (a.n_rows > 0)
-        k_prep<<<(unsigned)((a.n_rows + PREP_PRIMS - 1) / PREP_PRIMS), PREP_THREADS, 0, st>>>(
+    // small canvases: one extra binning workgroup orders the tiles by the previous forward's
+    // list lengths, off the critical path; larger ones: k_order on this forward's lengths
+    const bool order_in_prep = a.order && a.n_tiles <= ORDER_IN_PREP_MAX;
+    const long long blocks = (a.n_rows + PREP_PRIMS - 1) / PREP_PRIMS + (order_in_prep ? 1 : 0);
+    if (blocks > 0)
+        k_prep<<<(unsigned)blocks, PREP_THREADS, 0, st>>>(
             a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
-            a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags);
+            a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags, a.n_tiles,
+            order_in_prep ? a.order : nullptr, a.prev_len);
+    if (a.order && !order_in_prep && a.n_tiles > 0)
+        k_order<<<1, ORDER_BINS, 0, st>>>(a.tile_count, a.n_tiles, a.order);
     return hipGetLastError();
 }
 

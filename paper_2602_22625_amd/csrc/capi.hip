@@ -270,12 +270,10 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ba.box = (int *)c->box.p; ba.recs = (PrimRec *)c->recs.p;
     ba.tile_count = (int *)c->tile_count.p; ba.lists = (int *)c->lists.p;
     ba.list_cap = c->list_cap; ba.flags = (int *)c->flags.p; ba.pad_atlas = false;
+    ba.order = c->sched != SCHED_GRID ? (int *)c->order.p : nullptr;
+    ba.prev_len = (const int *)c->tile_len.p;
     hipError_t e = launch_binning(ba, st);
     if (e != hipSuccess) return hip_fail(c, e, "binning launch");
-    if (c->sched != SCHED_GRID) {
-        e = launch_order((const int *)c->tile_count.p, (int)tiles, (int *)c->order.p, st);
-        if (e != hipSuccess) return hip_fail(c, e, "order launch");
-    }
 
     RasterArgs &ra = c->ra;
     ra = RasterArgs{};

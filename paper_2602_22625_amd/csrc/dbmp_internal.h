@@ -116,6 +116,8 @@ struct BinArgs {
     int list_cap;
     int *flags;
     bool pad_atlas;    // pad the atlas and find its boxes (false: reuse the stored ones)
+    int *order;        // non-null: tiles by decreasing list length are written here
+    const int *prev_len;  // the previous forward's list lengths (any values: only the order uses them)
 };
 
 struct RasterArgs {
@@ -158,8 +160,6 @@ struct RasterArgs {
 enum { SCHED_GRID = 0, SCHED_SORTED = 1, SCHED_PERSISTENT = 2 };
 
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);
-// order[0 .. n_tiles): tiles by decreasing list length (counting sort of tile_count).
-hipError_t launch_order(const int *tile_count, int n_tiles, int *order, hipStream_t st);
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_fill0(float *p, long long n, hipStream_t st);

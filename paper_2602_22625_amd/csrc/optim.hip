@@ -81,16 +81,17 @@ k_adam(float *__restrict__ p, float *__restrict__ g, float *__restrict__ m,
         const float mhat = mi / c1, vhat = vi / c2;
         p[i] = p[i] - lr * mhat / (sqrtf(vhat) + eps);
     }
-    // The last block to finish advances the step counter (every block has read it by then)
-    // and re-arms the completion counter for the next call.
+    // The last block to finish advances the step counter and re-arms the completion counter
+    // for the next call. Every block read the step counter (and consumed the value) before its
+    // barrier and counts itself done after it, so the last block writes after every read. No
+    // fence: nothing else flows between blocks, and on gfx950 a device-scope fence writes back
+    // the L2 (once per block it would dominate this kernel).
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(done, 1u) == gridDim.x - 1) {
-            *step = t;
-            *done = 0u;
-            __threadfence();
-        }
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            gridDim.x - 1) {
+        *step = t;
+        *done = 0u;
     }
 }
 

@@ -266,13 +266,13 @@ __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__r
             body(order[item]);
         }
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
-            queue[0] = 0;
-            queue[1] = 0;
-            __threadfence();
-        }
+    // No fence: no data flows through the queue, and the last workgroup to leave knows that
+    // every other one has taken its final item (it left the loop before counting itself out).
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(queue + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            (int)gridDim.x - 1) {
+        queue[0] = 0;
+        queue[1] = 0;
     }
 }
 
@@ -297,6 +297,11 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
     __shared__ __attribute__((aligned(16))) int s_ids[CAP + 4];
     __shared__ PrimRec s_rec[BATCH];
     __shared__ float s_loss[TS * TS / 64];
+    __shared__ float s_grad[FUSED ? BATCH * 8 : 1];  // the backward's per-entry partial sums
+    if constexpr (FUSED) {
+        for (int i = threadIdx.x; i < BATCH * 8; i += NT) s_grad[i] = 0.f;
+        __syncthreads();
+    }
     auto tile_body = [&](const int tile) {
         const int n = tile_count[tile];
         __syncthreads();  // every lane has read the count before it is re-armed
@@ -416,13 +421,15 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         const int lane = threadIdx.x & 63;
         const bool staged = n <= BATCH;  // the forward's only batch is still in s_rec
         if (in_lds)
-            bwd_walk<NT, TexT, false>(n, [&](int j) { return s_ids[j]; }, staged, s_rec, recs,
+            bwd_walk<NT, TexT, false>(n, [&](int j) { return s_ids[j]; }, staged, s_rec, s_grad,
+                                      recs,
                                       atlas, Wp, tg, vmask, g0, g1, g2, 0.f, b0, b1, b2,
                                       tg.valid ? K : -1, TK, dparams, cu1, cv1, cu_cv, cv_cu,
                                       lane);
         else
             bwd_walk<NT, TexT, false>(n, [&](int j) { return ((volatile int *)seg)[j]; },
-                                      staged, s_rec, recs, atlas, Wp, tg, vmask, g0, g1, g2,
+                                      staged, s_rec, s_grad, recs, atlas, Wp, tg, vmask, g0,
+                                      g1, g2,
                                       0.f, b0, b1, b2, tg.valid ? K : -1, TK, dparams, cu1, cv1,
                                       cu_cv, cv_cu, lane);
         const float ws = wave_sum(sq);
@@ -441,10 +448,16 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 // The backward's walk over a tile's sorted list (entry j's id is id_at(j)), back to front in
 // batches of 64 entries (Supp. Eqs. S4-S5, Eq. 7): per pixel, g = dL/dI, ga = dL/dA, G = the
 // background, and the forward's (K, T_K). `staged`: the whole list (n <= 64) is already in
-// s_rec, staged by the forward of the fused step.
+// s_rec, staged by the forward of the fused step. The waves add their reduced partials into
+// s_grad (LDS, one float per staged entry and parameter, zero on entry), which is flushed to
+// dparams with one global atomic per (entry, parameter) after each batch: the tile's waves share
+// one global add, and no global atomic is outstanding while a wave waits for its texels (on
+// gfx950 the vector-memory counter retires in order, so a texel wait would also wait for the
+// acknowledgement of every earlier atomic).
 template <int NT, typename TexT, bool HAS_GA, int TS, typename IdAt>
 __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          PrimRec *__restrict__ s_rec,
+                                         float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
                                          const TexT *__restrict__ atlas, int Wp,
                                          const TileGeom<TS> &tg, uint64_t vmask, float g0,
@@ -511,7 +524,16 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             G2 = fmaf(m, G2, a * cb);
             Bk *= m;
             const float tot = reduce8(d, lane);
-            if ((lane & 7) == 0) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + (lane >> 3), tot);
+            if ((lane & 7) == 0)
+                __hip_atomic_fetch_add(s_grad + e * 8 + (lane >> 3), tot, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        // every wave has added its partials: one global atomic per (entry, parameter) per tile
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt * 8; t += NT) {
+            const float v = s_grad[t];
+            s_grad[t] = 0.f;  // ready for the next batch
+            if (v != 0.f) unsafeAtomicAdd(dparams + (size_t)s_rec[t >> 3].id * 8 + (t & 7), v);
         }
     }
 }
@@ -533,6 +555,9 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
 {
     __shared__ PrimRec s_rec[BATCH];
     __shared__ float s_loss[TS * TS / 64];
+    __shared__ float s_grad[BATCH * 8];  // per-entry partial sums of the gradient
+    for (int i = threadIdx.x; i < BATCH * 8; i += TS * TS) s_grad[i] = 0.f;
+    __syncthreads();
     auto tile_body = [&](const int tile) {
         const int n = tile_len[tile];
         if (n > list_cap) return;  // the forward did not render this tile
@@ -567,7 +592,8 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             TK = saveT[gp];
         }
         const int *seg = lists + (size_t)tile * list_cap;
-        bwd_walk<TS * TS, TexT, HAS_GA>(n, [&](int j) { return seg[j]; }, false, s_rec, recs,
+        bwd_walk<TS * TS, TexT, HAS_GA>(n, [&](int j) { return seg[j]; }, false, s_rec, s_grad,
+                                        recs,
                                         atlas, Wp, tg, vmask, g0, g1, g2, ga, G0, G1, G2, K, TK,
                                         dparams, cu1, cv1, cu_cv, cv_cu, lane);
         if (MSE) {

@@ -388,6 +388,37 @@ def test_batched_mse_backward_matches_oracle(sched, tile):
         assert_grads(out[p0:p0 + N], gref)
 
 
+def test_longest_first_order_from_binning_and_from_its_own_kernel():
+    """The longest-list-first tile order is computed by an extra binning workgroup from the
+    previous forward's lengths up to 4,096 tiles and by a kernel of its own beyond: images equal
+    the grid order's bitwise on both paths (4,096 and 4,225 tiles) and on a small canvas, over
+    repeated forwards (the first with no previous lengths) and fused steps."""
+    from paper_2602_22625_amd import capi
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c1")
+    p, idx, a = to_dev(d)
+    t = torch.tensor(d["target"], device="cuda")
+    for S, tile in [(512, 8), (520, 8), (128, 16)]:
+        R0, R1 = Renderer(), Renderer()
+        R1.set_schedule(capi.DBMP_SCHED_SORTED)
+        tS = torch.nn.functional.pad(t, (0, max(0, S - 512), 0, max(0, S - 512)))[:, :S, :S]
+        tS = tS.contiguous()
+        for k in range(3):
+            q = p + 0.25 * k
+            i0, a0 = R0.render(q, idx, a, S, S, None, 1.0, tile)
+            i1, a1 = R1.render(q, idx, a, S, S, None, 1.0, tile)
+            torch.cuda.synchronize()
+            assert torch.equal(i0, i1) and torch.equal(a0, a1), (S, tile, k)
+            f0, g0 = R0.render_mse(q, idx, a, S, S, tS, None, 1.0, tile)
+            f1, g1 = R1.render_mse(q, idx, a, S, S, tS, None, 1.0, tile)
+            R0.check()
+            R1.check()
+            assert torch.equal(f0, f1), (S, tile, k)
+            a0_, a1_ = g0.cpu().numpy().astype(np.float64), g1.cpu().numpy().astype(np.float64)
+            scale = np.abs(a0_).max(axis=0) + 1e-30  # per column: atomics in another order
+            assert np.all(np.abs(a0_ - a1_) <= 1e-5 * scale), (S, tile, k)
+
+
 def test_autograd_function_matches_oracle(R):
     from paper_2602_22625_amd.render import render
     d = synth.make_workload("c0")
