@@ -6,9 +6,10 @@
 //              sampler) and finds each bitmap's tight non-zero box (once per atlas);
 //   k_prep     per primitive: sigmoid/exp/sincos, the inverse affine map of Eqs. (1)-(2) folded
 //              into U' = aU x + bU y + eU (float64), the exact support parallelogram and its
-//              tile span; then sixteen lanes per primitive walk the span, test each tile (a
-//              separating-axis test, so rotated primitives are not charged for the corners of
-//              their bounding box) and append the primitive's row to the tile's list.
+//              tile span; then the workgroup deals the (primitive, tile) pairs of its spans
+//              over all its lanes, tests each tile (a separating-axis test, so rotated
+//              primitives are not charged for the corners of their bounding box) and appends
+//              the primitive's row to the tile's list.
 // Every tile owns a list of fixed capacity (lists[t * cap .. ]), so appending needs one atomic
 // per (tile, primitive) pair and no prefix scan or second pass; a tile whose list would
 // overflow raises a flag and the caller grows the capacity. The forward raster kernel sorts
@@ -193,8 +194,10 @@ k_order(const int *__restrict__ tile_count, int n_tiles, int *__restrict__ order
 // k_prep
 // ------------------------------------------------------------------------------------------
 #define PREP_THREADS 256
-#define PREP_PRIMS 16    // primitives per workgroup: 16 lanes compute records, all walk tiles
-#define TILE_LANES 16
+// Primitives per workgroup (PP): PP lanes of the first wave compute records, all lanes walk
+// tiles. 16 for small primitive counts (more workgroups in flight), 64 for large ones (a quarter
+// of the workgroups, each with as short a critical path).
+constexpr int PREP_SMALL_N = 16384;
 
 // The fields of a record the tile walk needs, kept in LDS between the two phases of k_prep.
 struct WalkRec {
@@ -202,6 +205,7 @@ struct WalkRec {
     int tx0, tx1, ty0, ty1, tile_off, ntx, W, H;
 };
 
+template <int PREP_PRIMS>
 __global__ void __launch_bounds__(PREP_THREADS)
 k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long n_rows,
        const ImgDev *__restrict__ imgs, int n_images, const int *__restrict__ box, int B, int Hb,
@@ -219,6 +223,8 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
         return;
     }
     __shared__ WalkRec s_rec[PREP_PRIMS];
+    __shared__ int s_span[PREP_PRIMS + 1];  // exclusive prefix sums of the tile spans, then the total
+    int span = 0;                           // this record lane's primitive: tiles in its span
     if (threadIdx.x < PREP_PRIMS) {
         const long long g = (long long)blockIdx.x * PREP_PRIMS + threadIdx.x;
         PrimRec rec;
@@ -326,28 +332,41 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
         wr.eV = rec.eV; wr.Ulo = rec.Ulo; wr.Uhi = rec.Uhi; wr.Vlo = rec.Vlo; wr.Vhi = rec.Vhi;
         wr.tx0 = rec.tx0; wr.tx1 = rec.tx1; wr.ty0 = rec.ty0; wr.ty1 = rec.ty1;
         wr.tile_off = rec.tile_off; wr.ntx = rec.ntx; wr.W = rec.W; wr.H = rec.H;
+        if (rec.tx0 <= rec.tx1) span = (rec.tx1 - rec.tx0 + 1) * (rec.ty1 - rec.ty0 + 1);
+    }
+    if (threadIdx.x < 64) {  // wave 0: scan of the spans (lanes past PREP_PRIMS add 0)
+        int x = span;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if ((int)threadIdx.x >= o) x += y;
+        }
+        if (threadIdx.x < PREP_PRIMS) s_span[threadIdx.x] = x - span;
+        if (threadIdx.x == PREP_PRIMS - 1) s_span[PREP_PRIMS] = x;
     }
     __syncthreads();
-    // Sixteen lanes per primitive walk its tile span and append it to every tile it hits.
-    const int lane = threadIdx.x % TILE_LANES;
-    for (int q = 0; q < PREP_PRIMS * TILE_LANES / PREP_THREADS; ++q) {
-        const int pl = q * (PREP_THREADS / TILE_LANES) + (int)threadIdx.x / TILE_LANES;
+    // The (primitive, tile of its span) pairs of the workgroup's primitives are dealt over all
+    // its threads, so a primitive spanning many tiles does not serialise its appends (returning
+    // atomics) on a few lanes; each hit appends the primitive's row to the tile's list.
+    const int total = s_span[PREP_PRIMS];
+    for (int k = threadIdx.x; k < total; k += PREP_THREADS) {
+        int pl = 0;  // the primitive whose span holds pair k: last pl with s_span[pl] <= k
+#pragma unroll
+        for (int step = PREP_PRIMS / 2; step > 0; step >>= 1)
+            if (s_span[pl + step] <= k) pl += step;
         const WalkRec &r = s_rec[pl];
-        if (r.tx0 > r.tx1) continue;
         const int g = (int)((long long)blockIdx.x * PREP_PRIMS + pl);
-        const int nx = r.tx1 - r.tx0 + 1, ny = r.ty1 - r.ty0 + 1;
-        for (int k = lane; k < nx * ny; k += TILE_LANES) {
-            const int tx = r.tx0 + k % nx, ty = r.ty0 + k / nx;
-            const int X0 = tx * TS, X1 = min(X0 + TS - 1, r.W - 1);
-            const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, r.H - 1);
-            if (!tile_hits(r, X0, X1, Y0, Y1)) continue;
-            const int tt = r.tile_off + ty * r.ntx + tx;
-            const int pos = atomicAdd(&tile_count[tt], 1);
-            if (pos < list_cap) {
-                lists[(size_t)tt * list_cap + pos] = g;
-            } else if (pos == list_cap) {  // the first entry that does not fit
-                flags[F_S_OVERFLOW] = 1;
-            }
+        const int kk = k - s_span[pl], nx = r.tx1 - r.tx0 + 1;
+        const int tx = r.tx0 + kk % nx, ty = r.ty0 + kk / nx;
+        const int X0 = tx * TS, X1 = min(X0 + TS - 1, r.W - 1);
+        const int Y0 = ty * TS, Y1 = min(Y0 + TS - 1, r.H - 1);
+        if (!tile_hits(r, X0, X1, Y0, Y1)) continue;
+        const int tt = r.tile_off + ty * r.ntx + tx;
+        const int pos = atomicAdd(&tile_count[tt], 1);
+        if (pos < list_cap) {
+            lists[(size_t)tt * list_cap + pos] = g;
+        } else if (pos == list_cap) {  // the first entry that does not fit
+            flags[F_S_OVERFLOW] = 1;
         }
     }
 }
@@ -369,12 +388,18 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
     // small canvases: one extra binning workgroup orders the tiles by the previous forward's
     // list lengths, off the critical path; larger ones: k_order on this forward's lengths
     const bool order_in_prep = a.order && a.n_tiles <= ORDER_IN_PREP_MAX;
-    const long long blocks = (a.n_rows + PREP_PRIMS - 1) / PREP_PRIMS + (order_in_prep ? 1 : 0);
-    if (blocks > 0)
-        k_prep<<<(unsigned)blocks, PREP_THREADS, 0, st>>>(
-            a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
-            a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags, a.n_tiles,
-            order_in_prep ? a.order : nullptr, a.prev_len);
+    auto prep = [&](auto kern, int pp) {
+        const long long blocks = (a.n_rows + pp - 1) / pp + (order_in_prep ? 1 : 0);
+        if (blocks > 0)
+            kern<<<(unsigned)blocks, PREP_THREADS, 0, st>>>(
+                a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
+                a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags,
+                a.n_tiles, order_in_prep ? a.order : nullptr, a.prev_len);
+    };
+    if (a.n_rows <= PREP_SMALL_N)
+        prep(k_prep<16>, 16);
+    else
+        prep(k_prep<64>, 64);
     if (a.order && !order_in_prep && a.n_tiles > 0)
         k_order<<<1, ORDER_BINS, 0, st>>>(a.tile_count, a.n_tiles, a.order);
     return hipGetLastError();
