@@ -213,6 +213,36 @@ int dbmp_render_batched_mse(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
                             const float *target, float *image, float *dL_dparams,
                             int accumulate);
 
+/*
+ * One Adam iteration of a fit (the MSE loss and Adam optimiser of Supp. Table S1) in two
+ * launches instead of three: the binning first applies to `params` the Adam update of the
+ * gradient the previous call left in `grad` (if `state` marks one pending), clearing it, and
+ * bins the updated parameters; the fused forward + MSE backward of dbmp_render_mse then adds
+ * the new gradient into `grad` and marks it pending. The stored atlas is used (dbmp_set_atlas).
+ *   params       in/out, device float32 [N, 8].
+ *   grad, m, v   device float32 [N, 8]: the pending gradient and Adam's moments; grad must hold
+ *                zeros before the first call.
+ *   state        device int32 [4]: {updates applied t, internal counter, gradient pending,
+ *                unused}, zeros before the first call.
+ *   lr, beta1, beta2, eps  Adam's hyper-parameters (as dbmp_adam_step).
+ *   other arguments as dbmp_render_mse; image receives the forward's image.
+ * Update j computes exactly what dbmp_adam_step computes with the same t and zero_grad = 1. After
+ * the last call, dbmp_adam_step(..., state, zero_grad = 1) applies the pending gradient (then
+ * clear state[2]). dbmp_mse_loss reports the loss of the image rendered by the last call.
+ */
+int dbmp_fit_step(dbmp_ctx *ctx, dbmp_stream stream, float *params, const int32_t *atlas_idx,
+                  int N, int H, int W, const float *bg, int bg_per_pixel, float alpha_max,
+                  int tile, const float *target, float *image, float *grad, float *m, float *v,
+                  int32_t *state, float lr, float beta1, float beta2, float eps);
+
+/* dbmp_fit_step over a batch of images (dbmp_render_batched's layout; each image's loss is the
+ * mean over its own 3HW values; Adam updates every row below the largest prim_offset + N). */
+int dbmp_fit_step_batched(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
+                          const dbmp_image_desc *descs, float *params, const int32_t *atlas_idx,
+                          const float *bg, float alpha_max, int tile, const float *target,
+                          float *image, float *grad, float *m, float *v, int32_t *state, float lr,
+                          float beta1, float beta2, float eps);
+
 /* Synchronises `stream` and reports the device-side errors raised by any forward since the
  * previous dbmp_check: DBMP_EOVERFLOW (a tile list did not fit; that forward's image is not
  * valid), DBMP_EINVAL (atlas index out of range), DBMP_ENONFINITE, or DBMP_OK. The reported

@@ -58,6 +58,8 @@ def load():
         "dbmp_render_backward": ([P, P, P, P, P], I),
         "dbmp_render_mse": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P, P, I], I),
         "dbmp_render_batched_mse": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P, P, I], I),
+        "dbmp_fit_step": ([P, P, P, P, I, I, I, P, I, F, I, P, P, P, P, P, P, F, F, F, F], I),
+        "dbmp_fit_step_batched": ([P, P, I, P, P, P, P, F, I, P, P, P, P, P, P, F, F, F, F], I),
         "dbmp_render_backward_mse": ([P, P, P, P, P, I], I),
         "dbmp_mse_loss": ([P, P, P], I),
         "dbmp_render_batched": ([P, P, I, P, P, P, P, I, I, I, I, P, F, I, P, P], I),
@@ -170,6 +172,25 @@ def dbmp_render_batched_mse(ctx, stream, descs, params, atlas_idx, atlas, B, Hb,
                                                     ptr(bg), float(alpha_max), int(tile),
                                                     ptr(target), ptr(image), ptr(dL_dparams),
                                                     int(accumulate)))
+
+
+def dbmp_fit_step(ctx, stream, params, atlas_idx, N, H, W, bg, bg_per_pixel, alpha_max, tile,
+                  target, image, grad, m, v, state, lr, beta1, beta2, eps):
+    return _chk(ctx, load().dbmp_fit_step(ctx, stream, ptr(params), ptr(atlas_idx), int(N),
+                                          int(H), int(W), ptr(bg), int(bg_per_pixel),
+                                          float(alpha_max), int(tile), ptr(target), ptr(image),
+                                          ptr(grad), ptr(m), ptr(v), ptr(state), float(lr),
+                                          float(beta1), float(beta2), float(eps)))
+
+
+def dbmp_fit_step_batched(ctx, stream, descs, params, atlas_idx, bg, alpha_max, tile, target,
+                          image, grad, m, v, state, lr, beta1, beta2, eps):
+    arr = (ImageDesc * len(descs))(*descs)
+    return _chk(ctx, load().dbmp_fit_step_batched(ctx, stream, len(descs), arr, ptr(params),
+                                                  ptr(atlas_idx), ptr(bg), float(alpha_max),
+                                                  int(tile), ptr(target), ptr(image), ptr(grad),
+                                                  ptr(m), ptr(v), ptr(state), float(lr),
+                                                  float(beta1), float(beta2), float(eps)))
 
 
 def dbmp_render_backward(ctx, stream, dL_dimage, dL_dalpha, dL_dparams):

@@ -362,6 +362,7 @@ def evaluate(net, n_targets=64, plain_steps=500, learned_steps=100, seed=10 ** 6
             for s in range(steps):
                 f.step()  # the loss recorded at step s is that of the image before update s
                 f.R.mse_loss(hist[s:s + 1])
+            f.flush()  # the last step's update
             f._render()
             f.R.backward_mse(f.target, None, out=f.grad, accumulate=True)
             f.R.mse_loss(hist[steps:steps + 1])

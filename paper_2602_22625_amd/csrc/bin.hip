@@ -207,12 +207,12 @@ struct WalkRec {
 
 template <int PREP_PRIMS>
 __global__ void __launch_bounds__(PREP_THREADS)
-k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long n_rows,
+k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
        const ImgDev *__restrict__ imgs, int n_images, const int *__restrict__ box, int B, int Hb,
        int Wb, int Wp, float alpha_max, int TS, PrimRec *__restrict__ recs,
        int *__restrict__ tile_count, int *__restrict__ lists, int list_cap,
        int *__restrict__ flags, int n_tiles, int *__restrict__ order,
-       const int *__restrict__ prev_len)
+       const int *__restrict__ prev_len, AdamArgs adam, int n_prep_blocks)
 {
     if (order && blockIdx.x == gridDim.x - 1) {
         // the extra workgroup: tiles by decreasing list length of the previous forward, while
@@ -225,6 +225,9 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
     __shared__ WalkRec s_rec[PREP_PRIMS];
     __shared__ int s_span[PREP_PRIMS + 1];  // exclusive prefix sums of the tile spans, then the total
     int span = 0;                           // this record lane's primitive: tiles in its span
+    // a fit step's pending Adam update (wave-uniform: every workgroup reads the same flag)
+    const bool adam_on = adam.params && adam.state[2] != 0;
+    const int t_adam = adam_on ? adam.state[0] + 1 : 0;
     if (threadIdx.x < PREP_PRIMS) {
         const long long g = (long long)blockIdx.x * PREP_PRIMS + threadIdx.x;
         PrimRec rec;
@@ -239,13 +242,31 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
         rec.id = (int)g;
         rec.pad = 0;
         if (g < n_rows) {
+            float p[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
+            if (adam_on) {
+                // the previous step's update of this row, as k_adam computes it (zero_grad)
+                const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
+                const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const long long i = g * 8 + j;
+                    const float gi = adam.grad[i];
+                    adam.grad[i] = 0.f;
+                    const float mi = fmaf(adam.b1, adam.m[i], (1.f - adam.b1) * gi);
+                    const float vi = fmaf(adam.b2, adam.v[i], (1.f - adam.b2) * gi * gi);
+                    adam.m[i] = mi;
+                    adam.v[i] = vi;
+                    const float mhat = mi / c1, vhat = vi / c2;
+                    p[j] = p[j] - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
+                    adam.params[i] = p[j];
+                }
+            }
             const int b = find_by_prim(imgs, n_images, g);
             const ImgDev D = imgs[b];
             rec.img = b; rec.tile_off = D.tile_off; rec.ntx = D.ntx; rec.W = D.W; rec.H = D.H;
             if (g >= D.prim_off && g < D.prim_off + D.N) {
-                float p[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
                 const int k = idx[g];
                 bool ok = true;
                 if (k < 0 || k >= B) {
@@ -369,6 +390,16 @@ k_prep(const float *__restrict__ params, const int *__restrict__ idx, long long 
             flags[F_S_OVERFLOW] = 1;
         }
     }
+    // The last binning workgroup advances the step counter and clears the pending flag. Every
+    // workgroup read both before its barrier above and counts itself done after it (no fence:
+    // nothing else passes between workgroups).
+    if (adam_on && threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(adam.state + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            n_prep_blocks - 1) {
+        adam.state[0] = t_adam;
+        adam.state[2] = 0;
+        adam.state[1] = 0;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -389,12 +420,13 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
     // list lengths, off the critical path; larger ones: k_order on this forward's lengths
     const bool order_in_prep = a.order && a.n_tiles <= ORDER_IN_PREP_MAX;
     auto prep = [&](auto kern, int pp) {
-        const long long blocks = (a.n_rows + pp - 1) / pp + (order_in_prep ? 1 : 0);
+        const long long n_prep = (a.n_rows + pp - 1) / pp;
+        const long long blocks = n_prep + (order_in_prep ? 1 : 0);
         if (blocks > 0)
             kern<<<(unsigned)blocks, PREP_THREADS, 0, st>>>(
                 a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
                 a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags,
-                a.n_tiles, order_in_prep ? a.order : nullptr, a.prev_len);
+                a.n_tiles, order_in_prep ? a.order : nullptr, a.prev_len, a.adam, (int)n_prep);
     };
     if (a.n_rows <= PREP_SMALL_N)
         prep(k_prep<16>, 16);

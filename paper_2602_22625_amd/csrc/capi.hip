@@ -180,6 +180,7 @@ struct FuseMse {
     const float *target = nullptr;
     float *dparams = nullptr;
     bool accumulate = false;
+    AdamArgs adam{};  // dbmp_fit_step: the binning first applies the pending Adam update
 };
 
 int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> &descs,
@@ -271,6 +272,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ba.tile_count = (int *)c->tile_count.p; ba.lists = (int *)c->lists.p;
     ba.list_cap = c->list_cap; ba.flags = (int *)c->flags.p; ba.pad_atlas = false;
     ba.order = c->sched != SCHED_GRID ? (int *)c->order.p : nullptr;
+    ba.adam = fuse.adam;
     ba.prev_len = (const int *)c->tile_len.p;
     hipError_t e = launch_binning(ba, st);
     if (e != hipSuccess) return hip_fail(c, e, "binning launch");
@@ -305,10 +307,12 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
             if (e != hipSuccess) return hip_fail(c, e, "gradient clear");
         }
     }
+    ra.pending = fuse.adam.params ? fuse.adam.state + 2 : nullptr;
     e = launch_raster_fwd(ra, st);
     ra.ev_start = ra.ev_stop = nullptr;
     ra.target = nullptr;  // the saved state is that of a plain forward
     ra.dparams = nullptr;
+    ra.pending = nullptr;
     if (e != hipSuccess) {
         // the appended counts were not consumed: clear them for the next forward
         (void)hipStreamSynchronize(st);
@@ -492,6 +496,66 @@ int dbmp_render_batched_mse(dbmp_ctx *c, dbmp_stream stream, int n_images,
     f.accumulate = accumulate != 0;
     return render_impl(c, (hipStream_t)stream, d, params, atlas_idx, atlas, B, Hb, Wb,
                        atlas_dtype, bg, 0, alpha_max, tile, image, nullptr, f);
+}
+
+namespace {
+int adam_args(dbmp_ctx *c, long long n_rows, float *params, float *grad, float *m, float *v,
+              int32_t *state, float lr, float beta1, float beta2, float eps, AdamArgs &a)
+{
+    if (!state || (n_rows > 0 && (!params || !grad || !m || !v)))
+        return fail(c, DBMP_EINVAL, "params / grad / m / v / state is NULL");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(c, DBMP_EINVAL, "bad Adam hyper-parameters");
+    a.params = params; a.grad = grad; a.m = m; a.v = v; a.state = state;
+    a.lr = lr; a.b1 = beta1; a.b2 = beta2; a.eps = eps;
+    return DBMP_OK;
+}
+}  // namespace
+
+int dbmp_fit_step(dbmp_ctx *c, dbmp_stream stream, float *params, const int32_t *atlas_idx,
+                  int N, int H, int W, const float *bg, int bg_per_pixel, float alpha_max,
+                  int tile, const float *target, float *image, float *grad, float *m, float *v,
+                  int32_t *state, float lr, float beta1, float beta2, float eps)
+{
+    if (!c) return DBMP_EINVAL;
+    if (N < 0 || H < 1 || W < 1) return fail(c, DBMP_EINVAL, "bad N / H / W");
+    if (!target) return fail(c, DBMP_EINVAL, "target is NULL");
+    DeviceGuard g(c->device);
+    FuseMse f;
+    int rc = adam_args(c, N, params, grad, m, v, state, lr, beta1, beta2, eps, f.adam);
+    if (rc) return rc;
+    f.target = target;
+    f.dparams = grad;
+    f.accumulate = true;
+    std::vector<dbmp_image_desc> d(1);
+    d[0].H = H; d[0].W = W; d[0].N = N; d[0].reserved = 0;
+    d[0].prim_offset = 0; d[0].pixel_offset = 0;
+    return render_impl(c, (hipStream_t)stream, d, params, atlas_idx, nullptr, 0, 0, 0, 0, bg,
+                       bg_per_pixel ? 1 : 0, alpha_max, tile, image, nullptr, f);
+}
+
+int dbmp_fit_step_batched(dbmp_ctx *c, dbmp_stream stream, int n_images,
+                          const dbmp_image_desc *descs, float *params, const int32_t *atlas_idx,
+                          const float *bg, float alpha_max, int tile, const float *target,
+                          float *image, float *grad, float *m, float *v, int32_t *state, float lr,
+                          float beta1, float beta2, float eps)
+{
+    if (!c) return DBMP_EINVAL;
+    if (n_images < 1 || !descs) return fail(c, DBMP_EINVAL, "need n_images >= 1 descriptors");
+    if (!target) return fail(c, DBMP_EINVAL, "target is NULL");
+    DeviceGuard g(c->device);
+    long long rows = 0;
+    for (int i = 0; i < n_images; ++i)
+        rows = std::max(rows, (long long)descs[i].prim_offset + descs[i].N);
+    FuseMse f;
+    int rc = adam_args(c, rows, params, grad, m, v, state, lr, beta1, beta2, eps, f.adam);
+    if (rc) return rc;
+    f.target = target;
+    f.dparams = grad;
+    f.accumulate = true;
+    std::vector<dbmp_image_desc> d(descs, descs + n_images);
+    return render_impl(c, (hipStream_t)stream, d, params, atlas_idx, nullptr, 0, 0, 0, 0, bg, 0,
+                       alpha_max, tile, image, nullptr, f);
 }
 
 int dbmp_render_backward(dbmp_ctx *c, dbmp_stream stream, const float *dL_dimage,

@@ -96,6 +96,14 @@ template <> __device__ __forceinline__ float texel<uint16_t>(uint16_t v)
 }
 
 // Launch arguments shared by the host code and the launchers.
+// Adam applied by the binning to a gradient left pending by the previous fit step (see
+// dbmp_fit_step): params non-null enables it.
+struct AdamArgs {
+    float *params, *grad, *m, *v;
+    int *state;  // {updates applied, workgroups done, gradient pending, unused}
+    float lr, b1, b2, eps;
+};
+
 struct BinArgs {
     const float *params;
     const int *idx;
@@ -116,6 +124,7 @@ struct BinArgs {
     int list_cap;
     int *flags;
     bool pad_atlas;    // pad the atlas and find its boxes (false: reuse the stored ones)
+    AdamArgs adam;     // adam.params non-null: apply the pending Adam update first
     int *order;        // non-null: tiles by decreasing list length are written here
     const int *prev_len;  // the previous forward's list lengths (any values: only the order uses them)
 };
@@ -150,6 +159,7 @@ struct RasterArgs {
     const int *order;                  // tiles by decreasing list length (SORTED, PERSISTENT)
     int *queue;                        // persistent work queues: fwd {head, done}, bwd {head, done}
     hipEvent_t ev_start, ev_stop;      // non-null: recorded by the device around the raster launch
+    int *pending;                      // fused fit step: set to 1 (a gradient awaits its update)
 };
 
 // How the raster kernels map workgroups to tiles.

@@ -291,9 +291,12 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
              unsigned long long *__restrict__ pair_counter, int sched, int grab,
              const int *__restrict__ order, int *__restrict__ queue,
              const float *__restrict__ target, float *__restrict__ loss_tile,
-             float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu)
+             float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
+             int *__restrict__ pending)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
+    // a fit step's gradient now awaits its Adam update (applied by the next binning)
+    if (FUSED && pending && blockIdx.x == 0 && threadIdx.x == 0) *pending = 1;
     __shared__ __attribute__((aligned(16))) int s_ids[CAP + 4];
     __shared__ PrimRec s_rec[BATCH];
     __shared__ float s_loss[TS * TS / 64];
@@ -660,7 +663,8 @@ static void fwd_t(const RasterArgs &a, hipStream_t st)
         a.imgs,
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
         a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue, a.target,
-        a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu));
+        a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu),
+        a.pending);
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA, bool MSE>

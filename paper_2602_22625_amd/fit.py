@@ -18,7 +18,7 @@ from .render import Renderer
 class Fitter:
     def __init__(self, params, atlas_idx, atlas, target, bg=None, alpha_max=1.0, tile=16,
                  lr=1e-2, betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0,
-                 accumulate=True, fused=True):
+                 accumulate=True, fused=True, adam_in_binning=True):
         dev = params.device
         self.H, self.W = int(target.shape[1]), int(target.shape[2])
         self.params = params.detach().clone().contiguous()
@@ -31,7 +31,8 @@ class Fitter:
         self.lr, self.betas, self.eps = lr, betas, eps
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
-        self.step_count = torch.zeros(2, dtype=torch.int32, device=dev)  # [steps, scratch]
+        # [updates applied, scratch counter, gradient pending, unused]
+        self.step_count = torch.zeros(4, dtype=torch.int32, device=dev)
         self.grad = torch.zeros_like(self.params)
         self.image = torch.empty(3, self.H, self.W, device=dev, dtype=torch.float32)
         self.loss_buf = torch.zeros(1, device=dev, dtype=torch.float32)
@@ -39,12 +40,16 @@ class Fitter:
         self.headroom = headroom
         self.accumulate = accumulate  # backward adds into grad, Adam zeroes it (no clear kernel)
         self.fused = fused  # forward and MSE backward in one launch (dbmp_render_mse)
+        # the binning applies the previous step's Adam update (dbmp_fit_step): two launches per
+        # step; the last gradient stays pending until flush()
+        self.adam_in_binning = fused and accumulate and adam_in_binning
         self.graph = None
         self._sized = False
 
-    # One Adam iteration, enqueued on the current stream: forward (the atlas was stored once),
-    # backward with the MSE gradient formed inside the kernel and accumulated into a gradient
-    # buffer that Adam zeroes after reading: four kernels per step.
+    # One Adam iteration, enqueued on the current stream. dbmp_fit_step: binning (with the
+    # pending Adam update) and the fused forward + MSE backward. Otherwise: forward (the atlas was
+    # stored once), the MSE backward (fused into the forward or a launch of its own) accumulating
+    # into a gradient buffer, and Adam, which zeroes it.
     def _render(self):
         self.R.render(self.params, self.atlas_idx, None, self.H, self.W, self.bg,
                       self.alpha_max, self.tile, image=self.image, with_alpha=False)
@@ -54,8 +59,27 @@ class Fitter:
                           self.bg, self.alpha_max, self.tile, image=self.image, out=self.grad,
                           accumulate=self.accumulate)
 
+    def _fit_step(self, st):
+        capi.dbmp_fit_step(self.R.ctx, st, self.params, self.atlas_idx, self.N, self.H, self.W,
+                           self.bg, 0 if self.bg.numel() == 3 else 1, self.alpha_max, self.tile,
+                           self.target, self.image, self.grad, self.m, self.v, self.step_count,
+                           self.lr, self.betas[0], self.betas[1], self.eps)
+        self.R._fwd_buffers = (self.image, self.bg)
+
+    def flush(self):
+        """Apply the Adam update of a gradient left pending by the last step (synchronises)."""
+        if self.adam_in_binning and int(self.step_count[2].item()):
+            capi.dbmp_adam_step(capi.stream_handle(), self.params, self.grad, self.m, self.v,
+                                self.params.numel(), self.lr, self.betas[0], self.betas[1],
+                                self.eps, self.step_count, zero_grad=1)
+            self.step_count[2] = 0
+        return self
+
     def _enqueue(self):
         st = capi.stream_handle()
+        if self.adam_in_binning:
+            self._fit_step(st)
+            return
         if self.fused:
             self._render_mse()
         else:
@@ -136,7 +160,7 @@ class Fitter:
                 raise capi.DbmpError(rc, capi.dbmp_last_error(self.R.ctx))
             done += k
             snap = self.snapshot()
-        return self
+        return self.flush()
 
     def check(self):
         """Synchronise and raise on device-side errors (overflow included)."""
@@ -193,7 +217,8 @@ class BatchFitter(Fitter):
     (white)."""
 
     def __init__(self, fits, atlas, bg=None, alpha_max=1.0, tile=16, lr=1e-2,
-                 betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0, fused=True):
+                 betas=(0.9, 0.999), eps=1e-8, renderer=None, headroom=2.0, fused=True,
+                 adam_in_binning=True):
         dev = fits[0][0].device
         self.descs = []
         prim, pix = 0, 0
@@ -213,7 +238,7 @@ class BatchFitter(Fitter):
         self.lr, self.betas, self.eps = lr, betas, eps
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
-        self.step_count = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.step_count = torch.zeros(4, dtype=torch.int32, device=dev)
         self.grad = torch.zeros_like(self.params)
         self.image = torch.empty(3 * pix, device=dev, dtype=torch.float32)
         self.loss_buf = torch.zeros(self.n_images, device=dev, dtype=torch.float32)
@@ -221,12 +246,24 @@ class BatchFitter(Fitter):
         self.headroom = headroom
         self.accumulate = True
         self.fused = fused
+        self.adam_in_binning = fused and adam_in_binning
         self.graph = None
         self._sized = False
 
     def _render(self):
         self.R.render_batched(self.descs, self.params, self.atlas_idx, None, self.bg,
                               self.alpha_max, self.tile, image=self.image, with_alpha=False)
+
+    def _fit_step(self, st):
+        capi.dbmp_fit_step_batched(self.R.ctx, st, self._cdescs(), self.params, self.atlas_idx,
+                                   self.bg, self.alpha_max, self.tile, self.target, self.image,
+                                   self.grad, self.m, self.v, self.step_count, self.lr,
+                                   self.betas[0], self.betas[1], self.eps)
+        self.R._fwd_buffers = (self.image, self.bg)
+
+    def _cdescs(self):
+        return [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))
+                for (h, w, n, po, xo) in self.descs]
 
     def _render_mse(self):
         self.R.render_batched_mse(self.descs, self.params, self.atlas_idx, None, self.bg,

@@ -132,6 +132,7 @@ def test_accumulating_step_matches_overwriting_step():
     for _ in range(5):
         fa.step()
         fo.step()
+    fa.flush()  # the last step's update is applied by the next binning, or here
     torch.cuda.synchronize()
     diff = (fa.params - fo.params).abs()
     # Adam's first steps move each parameter by about lr * sign(g); a gradient component that
@@ -382,3 +383,88 @@ def test_fitter_fused_matches_unfused():
         assert abs(f1.loss() - f2.loss()) <= 1e-4 * f1.loss()
     f1.check()
     f2.check()
+
+
+# ------------------------------------------------------------------------------------------
+# Adam applied by the binning (dbmp_fit_step): two launches per fit step
+# ------------------------------------------------------------------------------------------
+def test_adam_in_binning_is_adam_bit_for_bit():
+    """A pending gradient applied by the binning of dbmp_fit_step gives the parameters and
+    moments dbmp_adam_step gives with the same step counter, bit for bit; the counter advances
+    and the pending flag clears."""
+    from paper_2602_22625_amd.render import Renderer
+    d, (p, idx, a, t) = _fit_inputs("c1")
+    g = torch.randn(p.shape, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    g = g * 1e-3
+    m0 = torch.randn(p.shape, device="cuda") * 1e-4
+    v0 = torch.rand(p.shape, device="cuda") * 1e-6
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    # reference: the Adam kernel with t = 3 (state[0] = 2 updates applied)
+    pr, gr, mr, vr = p.clone(), g.clone(), m0.clone(), v0.clone()
+    sr = torch.tensor([2, 0, 0, 0], dtype=torch.int32, device="cuda")
+    capi.dbmp_adam_step(capi.stream_handle(), pr, gr, mr, vr, pr.numel(), lr, b1, b2, eps, sr,
+                        zero_grad=1)
+    # the same update inside the binning of a fit step, gradient pending
+    pf, gf, mf, vf = p.clone(), g.clone(), m0.clone(), v0.clone()
+    sf = torch.tensor([2, 0, 1, 0], dtype=torch.int32, device="cuda")
+    R = Renderer(check=False)
+    R.set_atlas(a)
+    img = torch.empty(3, 512, 512, device="cuda")
+    bg = torch.ones(3, device="cuda")
+    capi.dbmp_fit_step(R.ctx, capi.stream_handle(), pf, idx, pf.shape[0], 512, 512, bg, 0, 1.0,
+                       16, t, img, gf, mf, vf, sf, lr, b1, b2, eps)
+    R.check()
+    assert torch.equal(pf, pr) and torch.equal(mf, mr) and torch.equal(vf, vr)
+    assert sf.tolist() == [3, 0, 1, 0]  # advanced; the new gradient is pending
+    # the new gradient (accumulated into the cleared buffer) is that of the updated parameters
+    R2 = Renderer()
+    img2, g2 = R2.render_mse(pr, idx, a, 512, 512, t, None, 1.0, 16)
+    R2.check()
+    assert torch.equal(img, img2)
+    scale = g2.abs().amax(dim=0) + 1e-30
+    assert torch.all((gf - g2).abs() <= 1e-5 * scale)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_adam_in_binning_fit_matches_three_launch_fit(graph):
+    """Fits with Adam in the binning (two launches per step) and with a separate Adam launch
+    follow the same trajectory; after flush() the counter, gradient and flag are settled."""
+    from paper_2602_22625_amd.fit import Fitter
+    d, (p, idx, a, t) = _fit_inputs("c1")
+    f2 = Fitter(p, idx, a, t, tile=16)
+    f3 = Fitter(p, idx, a, t, tile=16, adam_in_binning=False)
+    assert f2.adam_in_binning and not f3.adam_in_binning
+    if graph:
+        f2.capture()
+        f3.capture()
+    for k in range(6):
+        f2.step()
+        f3.step()
+        l2, l3 = f2.loss(), f3.loss()
+        assert abs(l2 - l3) <= 1e-4 * l3, (k, l2, l3)
+    f2.flush()
+    f2.check()
+    f3.check()
+    assert f2.step_count.tolist()[:3] == [6, 0, 0] and f3.step_count.tolist()[:2] == [6, 0]
+    assert f2.grad.abs().max().item() == 0.0
+    diff = (f2.params - f3.params).abs()
+    assert diff.median().item() < 1e-6
+    assert (diff < 1e-5).float().mean().item() > 0.99
+
+
+def test_batched_adam_in_binning_matches_three_launch_batch():
+    from paper_2602_22625_amd.fit import BatchFitter
+    fits, atlas = _small_batch()
+    b2 = BatchFitter(fits, atlas)
+    b3 = BatchFitter(fits, atlas, adam_in_binning=False)
+    b2.capture()
+    for it in range(5):
+        b2.step()
+        b3.step()
+        l2, l3 = b2.losses(), b3.losses()
+        for k in range(len(fits)):
+            assert abs(l2[k] - l3[k]) <= 1e-4 * max(l3[k], 1e-12), (it, k, l2[k], l3[k])
+    b2.flush()
+    b2.check()
+    b3.check()
+    assert b2.step_count.tolist()[:3] == [5, 0, 0]
