@@ -246,21 +246,32 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
 #pragma unroll
             for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
             if (adam_on) {
-                // the previous step's update of this row, as k_adam computes it (zero_grad)
+                // the previous step's update of this row, as k_adam computes it (zero_grad);
+                // every load is issued before the first store (the buffers are distinct, but
+                // the compiler cannot know it, and would otherwise wait for each store)
                 const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
                 const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
+                float gv[8], mv[8], vv[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const long long i = g * 8 + j;
-                    const float gi = adam.grad[i];
-                    adam.grad[i] = 0.f;
-                    const float mi = fmaf(adam.b1, adam.m[i], (1.f - adam.b1) * gi);
-                    const float vi = fmaf(adam.b2, adam.v[i], (1.f - adam.b2) * gi * gi);
-                    adam.m[i] = mi;
-                    adam.v[i] = vi;
-                    const float mhat = mi / c1, vhat = vi / c2;
+                    gv[j] = adam.grad[g * 8 + j];
+                    mv[j] = adam.m[g * 8 + j];
+                    vv[j] = adam.v[g * 8 + j];
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float gi = gv[j];
+                    mv[j] = fmaf(adam.b1, mv[j], (1.f - adam.b1) * gi);
+                    vv[j] = fmaf(adam.b2, vv[j], (1.f - adam.b2) * gi * gi);
+                    const float mhat = mv[j] / c1, vhat = vv[j] / c2;
                     p[j] = p[j] - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
-                    adam.params[i] = p[j];
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    adam.grad[g * 8 + j] = 0.f;
+                    adam.m[g * 8 + j] = mv[j];
+                    adam.v[g * 8 + j] = vv[j];
+                    adam.params[g * 8 + j] = p[j];
                 }
             }
             const int b = find_by_prim(imgs, n_images, g);
