@@ -151,9 +151,12 @@ __device__ __forceinline__ void bilinear_all(const TexT *__restrict__ atlas, int
     blend_cell<TexT>(atlas + (tex + off), Wp, wu, wv, M, MU, MV);
 }
 
+// Lists up to this length are sorted in LDS, longer ones in place in global memory. At 512
+// entries for 8 x 8 and 16 x 16 tiles the buffer takes 2 KB; at 2,048 it limited the 16 x 16
+// forward to 7 workgroups per CU by LDS (lists at these workloads are far shorter).
 template <int TS>
 struct SortCap {
-    static constexpr int v = TS == 8 ? 512 : (TS == 16 ? 2048 : 4096);
+    static constexpr int v = TS == 32 ? 4096 : 512;
 };
 
 // Ascending bitonic network with only ascending comparators (the first sub-stage of every merge
@@ -238,11 +241,14 @@ __device__ __forceinline__ float wave_sum(float y)
 // finished the previous tile before its LDS is reused. The last workgroup to leave re-arms the
 // queue for the next launch. Persistent with grab == 0: workgroup w takes items w, w + G,
 // w + 2G, ... of the longest-first order (no atomics; the order balances the strides).
-template <typename Body>
+// PERSIST is a compile-time choice: a kernel built for the one-tile-per-workgroup schedules
+// carries none of the persistent loop's state, which keeps it at about 60 scalar registers
+// instead of over 100 (a limit on waves per SIMD).
+template <bool PERSIST, typename Body>
 __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__restrict__ order,
                                              int *__restrict__ queue, int n_tiles, Body body)
 {
-    if (sched != SCHED_PERSISTENT) {
+    if constexpr (!PERSIST) {
         body(sched == SCHED_SORTED ? order[blockIdx.x] : xcd_remap(blockIdx.x, n_tiles));
         return;
     }
@@ -280,7 +286,7 @@ __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__r
 // loss against `target` (the image, the per-pixel (K, T_K) and, for a list of at most 64
 // entries, the staged records are still on chip); the gradient is added to dparams and the
 // tile's squared error written to loss_tile.
-template <int TS, typename TexT, bool BG_PP, bool FUSED>
+template <int TS, typename TexT, bool BG_PP, bool FUSED, bool PERSIST>
 __global__ void __launch_bounds__(TS * TS)
 k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
              int *__restrict__ tile_count, int *__restrict__ tile_len, int *__restrict__ list_max,
@@ -445,7 +451,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         }
     }
     };
-    run_schedule(sched, grab, order, queue, n_tiles, tile_body);
+    run_schedule<PERSIST>(sched, grab, order, queue, n_tiles, tile_body);
 }
 
 // The backward's walk over a tile's sorted list (entry j's id is id_at(j)), back to front in
@@ -543,7 +549,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
 
 // MSE: the backward forms dL/dI = scale (I - target) itself from the forward's image and writes
 // the workgroup's sum of squared differences to loss_tile[tile] (reduced on request).
-template <int TS, typename TexT, bool BG_PP, bool HAS_GA, bool MSE>
+template <int TS, typename TexT, bool BG_PP, bool HAS_GA, bool MSE, bool PERSIST>
 __global__ void __launch_bounds__(TS * TS)
 k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, int list_cap,
              const int *__restrict__ tile_len,
@@ -610,7 +616,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             }
         }
     };
-    run_schedule(sched, grab, order, queue, n_tiles, tile_body);
+    run_schedule<PERSIST>(sched, grab, order, queue, n_tiles, tile_body);
 }
 
 __global__ void k_fill0(float *__restrict__ p, long long n)
@@ -658,7 +664,9 @@ static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
     const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
-    launch(k_raster_fwd<TS, TexT, BGPP, FUSED>, grid, TS * TS, st, a.ev_start, a.ev_stop,
+    auto kern = a.sched == SCHED_PERSISTENT ? k_raster_fwd<TS, TexT, BGPP, FUSED, true>
+                                            : k_raster_fwd<TS, TexT, BGPP, FUSED, false>;
+    launch(kern, grid, TS * TS, st, a.ev_start, a.ev_stop,
         a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len, a.list_max,
         a.imgs,
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
@@ -672,7 +680,9 @@ static void bwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
     const int grid = a.sched == SCHED_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
-    launch(k_raster_bwd<TS, TexT, BGPP, GA, MSE>, grid, TS * TS, st, a.ev_start, a.ev_stop,
+    auto kern = a.sched == SCHED_PERSISTENT ? k_raster_bwd<TS, TexT, BGPP, GA, MSE, true>
+                                            : k_raster_bwd<TS, TexT, BGPP, GA, MSE, false>;
+    launch(kern, grid, TS * TS, st, a.ev_start, a.ev_stop,
         a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
         (const TexT *)a.atlas_pad, a.Wp, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI, a.target,
         a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
