@@ -44,6 +44,7 @@ class Fitter:
         # step; the last gradient stays pending until flush()
         self.adam_in_binning = fused and accumulate and adam_in_binning
         self.graph = None
+        self._graph_steps = 1
         self._sized = False
 
     # One Adam iteration, enqueued on the current stream. dbmp_fit_step: binning (with the
@@ -101,12 +102,19 @@ class Fitter:
         self._sized = True
 
     def step(self):
+        """One replay of the captured graph (graph_steps Adam iterations), else one eager
+        iteration."""
         if not self._sized:
             self._size()
         if self.graph is not None:
             self.graph.replay()
         else:
             self._enqueue()
+
+    @property
+    def graph_steps(self):
+        """Adam iterations per step() call."""
+        return self._graph_steps if self.graph is not None else 1
 
     def _state(self):
         return [self.params, self.m, self.v, self.step_count, self.grad]
@@ -118,10 +126,14 @@ class Fitter:
         for t, c in zip(self._state(), snap):
             t.copy_(c)
 
-    def capture(self):
-        """Capture one Adam iteration into a HIP graph. A warm-up step runs first on a side
-        stream (first launches of every kernel, no workspace growth inside the capture); its
-        effect on the optimiser state is undone, so capturing does not alter the trajectory."""
+    def capture(self, steps_per_graph=1):
+        """Capture `steps_per_graph` Adam iterations into one HIP graph (replayed by step()):
+        several iterations per replay spread the host's replay cost, the optimiser state being
+        on the device. A warm-up step runs first on a side stream (first launches of every
+        kernel, no workspace growth inside the capture); its effect on the optimiser state is
+        undone, so capturing does not alter the trajectory."""
+        if steps_per_graph < 1:
+            raise ValueError("steps_per_graph must be >= 1")
         if not self._sized:
             self._size()
         snap = self.snapshot()
@@ -135,8 +147,10 @@ class Fitter:
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self._enqueue()
+            for _ in range(steps_per_graph):
+                self._enqueue()
         self.graph = g
+        self._graph_steps = steps_per_graph
 
     def run(self, steps, check_every=50):
         """`steps` Adam iterations; every `check_every` steps the device flags are polled. On a
@@ -145,8 +159,11 @@ class Fitter:
         snap = self.snapshot()
         while done < steps:
             k = min(check_every, steps - done)
-            for _ in range(k):
+            gs = self.graph_steps
+            for _ in range(k // gs):
                 self.step()
+            for _ in range(k % gs):  # the remainder eagerly
+                self._enqueue()
             rc = capi.dbmp_check(self.R.ctx, capi.stream_handle())
             if rc == capi.DBMP_EOVERFLOW:
                 self.restore(snap)
@@ -154,7 +171,7 @@ class Fitter:
                 capi.dbmp_reserve(self.R.ctx, int(need * max(self.headroom, 1.25)) + 1)
                 if self.graph is not None:
                     self.graph = None
-                    self.capture()
+                    self.capture(gs)
                 continue
             if rc != capi.DBMP_OK:
                 raise capi.DbmpError(rc, capi.dbmp_last_error(self.R.ctx))
@@ -248,6 +265,7 @@ class BatchFitter(Fitter):
         self.fused = fused
         self.adam_in_binning = fused and adam_in_binning
         self.graph = None
+        self._graph_steps = 1
         self._sized = False
 
     def _render(self):

@@ -468,3 +468,30 @@ def test_batched_adam_in_binning_matches_three_launch_batch():
     b2.check()
     b3.check()
     assert b2.step_count.tolist()[:3] == [5, 0, 0]
+
+
+def test_several_iterations_per_graph_replay():
+    """A graph of 4 Adam iterations replayed 3 times follows the trajectory of 12 one-iteration
+    replays; run() with such a graph and a poll interval that is not a multiple of it does the
+    requested number of iterations (the remainder eagerly)."""
+    from paper_2602_22625_amd.fit import Fitter
+    d, (p, idx, a, t) = _fit_inputs("c1")
+    f1 = Fitter(p, idx, a, t, tile=16)
+    f4 = Fitter(p, idx, a, t, tile=16)
+    f1.capture()
+    f4.capture(4)
+    assert f1.graph_steps == 1 and f4.graph_steps == 4
+    for k in range(3):
+        for _ in range(4):
+            f1.step()
+        f4.step()
+        l1, l4 = f1.loss(), f4.loss()
+        assert abs(l1 - l4) <= 1e-4 * l1, (k, l1, l4)
+    f1.flush()
+    f4.flush()
+    assert f1.step_count.tolist()[:3] == [12, 0, 0] and f4.step_count.tolist()[:3] == [12, 0, 0]
+    diff = (f1.params - f4.params).abs()
+    assert diff.median().item() < 1e-6
+    f4.run(10, check_every=6)
+    f4.check()
+    assert int(f4.step_count[0].item()) == 22
