@@ -199,7 +199,7 @@ def main():
     step_bytes = metrics.fused_algorithmic_bytes(H, W, N, atlas.numel() * 4)
     traffic = measured_traffic("k_raster_fused_512sq_4096prims_traffic.md")
     roofline = {
-        "kernel": "k_raster_fwd<16, float, false, true>: forward and MSE backward of a fit step "
+        "kernel": "k_raster_fwd<16, float, false, true, false>: forward and MSE backward of a fit step "
                   "in one launch (the timed steps' raster kernel)",
         "bound": "alu",
         "achieved": round(step_tflops, 4),
