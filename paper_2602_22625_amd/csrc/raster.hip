@@ -115,12 +115,19 @@ __device__ __forceinline__ uint64_t support_mask(const PrimRec &r, double U, dou
 // derivatives along U' and V' on the floor cell. Forward and backward evaluate the same
 // arithmetic (blend_cell), so both obtain bit-identical alpha (the backward's transmittance
 // recovery relies on it).
+// The cell is addressed by its 32-bit byte offset from the atlas base (atlases are far below
+// 4 GB): the loads then take the base from scalar registers and only the offset per lane, and the
+// offset costs one 24-bit multiply-add (texel coordinates and row pitches are below 2^24).
 template <typename TexT>
-__device__ __forceinline__ void blend_cell(const TexT *__restrict__ t, int Wp, float wu, float wv,
-                                           float &M, float &MU, float &MV)
+__device__ __forceinline__ void blend_cell(const TexT *__restrict__ atlas, unsigned elem, int Wp,
+                                           float wu, float wv, float &M, float &MU, float &MV)
 {
-    const float p00 = texel<TexT>(t[0]), p01 = texel<TexT>(t[1]);
-    const float p10 = texel<TexT>(t[Wp]), p11 = texel<TexT>(t[Wp + 1]);
+    const char *base = reinterpret_cast<const char *>(atlas);
+    const unsigned b0 = elem * (unsigned)sizeof(TexT);
+    const TexT *t0 = reinterpret_cast<const TexT *>(base + b0);
+    const TexT *t1 = reinterpret_cast<const TexT *>(base + (b0 + (unsigned)Wp * sizeof(TexT)));
+    const float p00 = texel<TexT>(t0[0]), p01 = texel<TexT>(t0[1]);
+    const float p10 = texel<TexT>(t1[0]), p11 = texel<TexT>(t1[1]);
     const float d0 = p01 - p00, d1 = p11 - p10;
     const float top = fmaf(wu, d0, p00);
     const float bot = fmaf(wu, d1, p10);
@@ -134,7 +141,8 @@ __device__ __forceinline__ void bilinear(const TexT *__restrict__ atlas, int tex
                                          double V, float &M, float &MU, float &MV)
 {
     const float wu = (float)__builtin_amdgcn_fract(U), wv = (float)__builtin_amdgcn_fract(V);
-    blend_cell<TexT>(atlas + (tex + (int)V * Wp + (int)U), Wp, wu, wv, M, MU, MV);
+    const unsigned cell = __umul24((unsigned)(int)V, (unsigned)Wp) + (unsigned)(int)U;
+    blend_cell<TexT>(atlas, (unsigned)tex + cell, Wp, wu, wv, M, MU, MV);
 }
 
 // The same for every lane of the wave: a lane outside the support samples the padded bitmap's
@@ -147,8 +155,8 @@ __device__ __forceinline__ void bilinear_all(const TexT *__restrict__ atlas, int
 {
     const float wu = in ? (float)__builtin_amdgcn_fract(U) : 0.f;
     const float wv = in ? (float)__builtin_amdgcn_fract(V) : 0.f;
-    const int off = in ? (int)V * Wp + (int)U : 0;
-    blend_cell<TexT>(atlas + (tex + off), Wp, wu, wv, M, MU, MV);
+    const unsigned cell = in ? __umul24((unsigned)(int)V, (unsigned)Wp) + (unsigned)(int)U : 0u;
+    blend_cell<TexT>(atlas, (unsigned)tex + cell, Wp, wu, wv, M, MU, MV);
 }
 
 // Lists up to this length are sorted in LDS, longer ones in place in global memory. At 512
@@ -463,6 +471,16 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 // one global add, and no global atomic is outstanding while a wave waits for its texels (on
 // gfx950 the vector-memory counter retires in order, so a texel wait would also wait for the
 // acknowledgement of every earlier atomic).
+//
+// The lanes sum only the factors that vary per pixel; the primitive's own constant factors are
+// applied once per entry at the flush (the sums are linear in them):
+//     s0 = sum dal MU,  s1 = sum dal MV      x, y:     -k_a (f_aU s0 + f_aV s1), -k_a (f_bU s0 + f_bV s1)
+//     s2 = sum dal (MU U_c + MV V_c)         log s:    -k_a s2
+//     s3 = sum dal (MU r V_c - MV U_c / r)   theta:    k_a s3
+//     s4 = sum dal M                         nu:       k_a (1 - sigma) s4 (kaom)
+//     s5..s7 = sum g_c T_j alpha_j           colours:  c (1 - c) s5..s7
+// with dal = dL/dalpha_j, U_c, V_c the bitmap coordinates about the centre and r the ratio of the
+// bitmap's half-extents.
 template <int NT, typename TexT, bool HAS_GA, int TS, typename IdAt>
 __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          PrimRec *__restrict__ s_rec,
@@ -476,7 +494,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          int lane)
 {
     const double xd = tg.px, yd = tg.py;
-    float Bk = 1.f, Trun = TK;
+    float Bk = 1.f, Trun = 0.f;  // behind K the transmittance is 0
     for (int hi = n; hi > 0; hi -= BATCH) {
         const int b0 = max(0, hi - BATCH), cnt = hi - b0;
         if (!(staged && b0 == 0)) {
@@ -504,33 +522,35 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             const float a = r.ka * M;
             const float m = 1.f - a;
             // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp;
-            // exactly 1 where alpha = 0)
-            float rc = __builtin_amdgcn_rcpf(m);
-            rc = fmaf(rc, fmaf(-m, rc, 1.f), rc);
-            const float Tj = j == K ? TK : (j < K ? Trun * rc : 0.f);
+            // exactly 1 where alpha = 0). In front of K, 1 - alpha_j >= TAU, so the clamp
+            // changes nothing there; behind K (running value 0) it keeps the reciprocal finite.
+            const float mc = fmaxf(m, 0x1p-126f);
+            float rc = __builtin_amdgcn_rcpf(mc);
+            rc = fmaf(rc, fmaf(-mc, rc, 1.f), rc);
+            const float Tj = j == K ? TK : Trun * rc;
             Trun = Tj;
-            const float cr = r.cr, cg = r.cg, cb = r.cb;
-            float dal = g0 * (cr - G0);
-            dal = fmaf(g1, cg - G1, dal);
-            dal = fmaf(g2, cb - G2, dal);
+            // c_j - G: the colour's lead over the composite behind it, which also advances G
+            // to the composite behind layer j - 1: G + alpha (c - G) = alpha c + (1 - alpha) G
+            const float e0 = r.cr - G0, e1 = r.cg - G1, e2 = r.cb - G2;
+            float dal = g0 * e0;
+            dal = fmaf(g1, e1, dal);
+            dal = fmaf(g2, e2, dal);
             if (HAS_GA) dal = fmaf(ga, Bk, dal);
             dal *= Tj;
             const float ta = Tj * a;
-            d[5] = g0 * ta * r.ccr;
-            d[6] = g1 * ta * r.ccg;
-            d[7] = g2 * ta * r.ccb;
-            d[4] = dal * r.kaom * M;
-            const float dM = dal * r.ka;
-            const float gU = dM * MU, gV = dM * MV;
+            d[5] = g0 * ta;
+            d[6] = g1 * ta;
+            d[7] = g2 * ta;
+            d[4] = dal * M;
+            const float gU = dal * MU, gV = dal * MV;
             const float Ub = (float)(U - cu1), Vb = (float)(V - cv1);
-            // negated operands (free source modifiers) rather than negated results
-            d[0] = fmaf(-gU, r.faU, -(gV * r.faV));
-            d[1] = fmaf(-gU, r.fbU, -(gV * r.fbV));
-            d[2] = fmaf(-gU, Ub, -(gV * Vb));
+            d[0] = gU;
+            d[1] = gV;
+            d[2] = fmaf(gU, Ub, gV * Vb);
             d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
-            G0 = fmaf(m, G0, a * cr);
-            G1 = fmaf(m, G1, a * cg);
-            G2 = fmaf(m, G2, a * cb);
+            G0 = fmaf(a, e0, G0);
+            G1 = fmaf(a, e1, G1);
+            G2 = fmaf(a, e2, G2);
             Bk *= m;
             const float tot = reduce8(d, lane);
             if ((lane & 7) == 0)
@@ -540,9 +560,25 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
         // every wave has added its partials: one global atomic per (entry, parameter) per tile
         __syncthreads();
         for (int t = threadIdx.x; t < cnt * 8; t += NT) {
+            const int q = t & 7;
+            if (q == 1) continue;  // written by the thread of parameter 0
+            const PrimRec &r = s_rec[t >> 3];
+            float *dst = dparams + (size_t)r.id * 8 + q;
             const float v = s_grad[t];
             s_grad[t] = 0.f;  // ready for the next batch
-            if (v != 0.f) unsafeAtomicAdd(dparams + (size_t)s_rec[t >> 3].id * 8 + (t & 7), v);
+            if (q == 0) {
+                const float w = s_grad[t + 1];
+                s_grad[t + 1] = 0.f;
+                const float gx = -r.ka * fmaf(r.faU, v, r.faV * w);
+                const float gy = -r.ka * fmaf(r.fbU, v, r.fbV * w);
+                if (gx != 0.f) unsafeAtomicAdd(dst, gx);
+                if (gy != 0.f) unsafeAtomicAdd(dst + 1, gy);
+            } else {
+                const float f = q == 2 ? -r.ka : q == 3 ? r.ka : q == 4 ? r.kaom
+                              : q == 5 ? r.ccr : q == 6 ? r.ccg : r.ccb;
+                const float x = f * v;
+                if (x != 0.f) unsafeAtomicAdd(dst, x);
+            }
         }
     }
 }
