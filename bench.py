@@ -35,7 +35,7 @@ def kernel_source_digest():
     """sha256 over the raster kernels' sources: identifies the code the counters were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("raster.hip", "dbmp_internal.h"):
+    for f in ("raster_kernels.h", "raster.hip", "raster_pipe.hip", "dbmp_internal.h"):
         with open(os.path.join(ROOT, "paper_2602_22625_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -199,7 +199,7 @@ def main():
     step_bytes = metrics.fused_algorithmic_bytes(H, W, N, atlas.numel() * 4)
     traffic = measured_traffic("k_raster_fused_512sq_4096prims_traffic.md")
     roofline = {
-        "kernel": "k_raster_fwd<16, float, false, true, false>: forward and MSE backward of a fit step "
+        "kernel": "k_raster_fwd<16, float, false, true, 2>: forward and MSE backward of a fit step "
                   "in one launch (the timed steps' raster kernel)",
         "bound": "alu",
         "achieved": round(step_tflops, 4),

@@ -295,6 +295,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.loss_tile = (float *)c->loss_tile.p;
     ra.sched = c->sched;
     ra.grid = c->n_cu * c->wgs_per_cu;
+    ra.n_cu = c->n_cu;
     ra.grab = c->grab;
     ra.order = (const int *)c->order.p;
     ra.queue = (int *)c->queue.p;

@@ -160,6 +160,7 @@ struct RasterArgs {
     int *queue;                        // persistent work queues: fwd {head, done}, bwd {head, done}
     hipEvent_t ev_start, ev_stop;      // non-null: recorded by the device around the raster launch
     int *pending;                      // fused fit step: set to 1 (a gradient awaits its update)
+    int n_cu;                          // compute units of the device (the walk form's choice)
 };
 
 // How the raster kernels map workgroups to tiles.
@@ -172,6 +173,9 @@ enum { SCHED_GRID = 0, SCHED_SORTED = 1, SCHED_PERSISTENT = 2 };
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);
+// the pipelined one-tile-per-workgroup build (raster_pipe.hip)
+hipError_t launch_raster_fwd_pipe(const RasterArgs &a, hipStream_t st);
+hipError_t launch_raster_bwd_pipe(const RasterArgs &a, hipStream_t st);
 hipError_t launch_fill0(float *p, long long n, hipStream_t st);
 hipError_t launch_loss_sum(const float *loss_tile, const ImgDev *imgs, int n_images, float *out,
                            hipStream_t st);
