@@ -222,8 +222,9 @@ int dbmp_render_batched_mse(dbmp_ctx *ctx, dbmp_stream stream, int n_images,
  *   params       in/out, device float32 [N, 8].
  *   grad, m, v   device float32 [N, 8]: the pending gradient and Adam's moments; grad must hold
  *                zeros before the first call.
- *   state        device int32 [4]: {updates applied t, internal counter, gradient pending,
- *                unused}, zeros before the first call.
+ *   state        device int32 [4]: {updates applied t, unused, gradient pending, unused}, zeros
+ *                before the first call (the fused launch counts the update the binning applied
+ *                and marks its own gradient pending).
  *   lr, beta1, beta2, eps  Adam's hyper-parameters (as dbmp_adam_step).
  *   other arguments as dbmp_render_mse; image receives the forward's image.
  * Update j computes exactly what dbmp_adam_step computes with the same t and zero_grad = 1. After

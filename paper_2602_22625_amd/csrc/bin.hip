@@ -212,7 +212,7 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
        int Wb, int Wp, float alpha_max, int TS, PrimRec *__restrict__ recs,
        int *__restrict__ tile_count, int *__restrict__ lists, int list_cap,
        int *__restrict__ flags, int n_tiles, int *__restrict__ order,
-       const int *__restrict__ prev_len, AdamArgs adam, int n_prep_blocks)
+       const int *__restrict__ prev_len, AdamArgs adam)
 {
     if (order && blockIdx.x == gridDim.x - 1) {
         // the extra workgroup: tiles by decreasing list length of the previous forward, while
@@ -242,22 +242,39 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
         rec.id = (int)g;
         rec.pad = 0;
         if (g < n_rows) {
-            float p[8];
+            // Every load that does not wait on another is issued first, so that their latencies
+            // overlap: the parameters, the inputs of a pending Adam update (read whenever the
+            // update buffers are given; used only if it is pending), the image record, the
+            // bitmap index and the bitmap's box. The Adam stores come after all of them (the
+            // buffers are distinct, but the compiler cannot know it, and would otherwise wait
+            // for each store).
+            float p[8], gv[8], mv[8], vv[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
-            if (adam_on) {
-                // the previous step's update of this row, as k_adam computes it (zero_grad);
-                // every load is issued before the first store (the buffers are distinct, but
-                // the compiler cannot know it, and would otherwise wait for each store)
-                const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
-                const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
-                float gv[8], mv[8], vv[8];
+            if (adam.params) {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     gv[j] = adam.grad[g * 8 + j];
                     mv[j] = adam.m[g * 8 + j];
                     vv[j] = adam.v[g * 8 + j];
                 }
+            }
+            const int b = find_by_prim(imgs, n_images, g);
+            const ImgDev D = imgs[b];
+            const int k = idx[g];
+            const bool k_ok = k >= 0 && k < B;
+            const int kb = k_ok ? k : 0;
+            int xlo = 0, xhi = -1, ylo = 0, yhi = -1;
+            if (k_ok) {
+                xlo = box[4 * kb];
+                xhi = box[4 * kb + 1];
+                ylo = box[4 * kb + 2];
+                yhi = box[4 * kb + 3];
+            }
+            if (adam_on) {
+                // the previous step's update of this row, as k_adam computes it (zero_grad)
+                const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
+                const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const float gi = gv[j];
@@ -274,13 +291,10 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
                     adam.params[g * 8 + j] = p[j];
                 }
             }
-            const int b = find_by_prim(imgs, n_images, g);
-            const ImgDev D = imgs[b];
             rec.img = b; rec.tile_off = D.tile_off; rec.ntx = D.ntx; rec.W = D.W; rec.H = D.H;
             if (g >= D.prim_off && g < D.prim_off + D.N) {
-                const int k = idx[g];
                 bool ok = true;
-                if (k < 0 || k >= B) {
+                if (!k_ok) {
                     atomicOr(&flags[F_S_BADIDX], 1);
                     ok = false;
                 }
@@ -320,9 +334,6 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
                     rec.ccb = (float)(c3[2] / (1.0 + exp((double)p[7])));
                     const int Hp = Hb + 2;
                     rec.tex = k * Hp * Wp;
-                    int xlo = box[4 * k];
-                    const int xhi = box[4 * k + 1];
-                    const int ylo = box[4 * k + 2], yhi = box[4 * k + 3];
                     if (xlo == INT_MIN) {  // the bitmap holds a non-finite texel (read as 0)
                         atomicOr(&flags[F_S_NONFINITE], 1);
                         xlo = 0;
@@ -401,16 +412,6 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
             flags[F_S_OVERFLOW] = 1;
         }
     }
-    // The last binning workgroup advances the step counter and clears the pending flag. Every
-    // workgroup read both before its barrier above and counts itself done after it (no fence:
-    // nothing else passes between workgroups).
-    if (adam_on && threadIdx.x == 0 &&
-        __hip_atomic_fetch_add(adam.state + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-            n_prep_blocks - 1) {
-        adam.state[0] = t_adam;
-        adam.state[2] = 0;
-        adam.state[1] = 0;
-    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -437,7 +438,7 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
             kern<<<(unsigned)blocks, PREP_THREADS, 0, st>>>(
                 a.params, a.idx, a.n_rows, a.imgs, a.n_images, a.box, a.B, a.Hb, a.Wb, a.Wp,
                 a.alpha_max, a.TS, a.recs, a.tile_count, a.lists, a.list_cap, a.flags,
-                a.n_tiles, order_in_prep ? a.order : nullptr, a.prev_len, a.adam, (int)n_prep);
+                a.n_tiles, order_in_prep ? a.order : nullptr, a.prev_len, a.adam);
     };
     if (a.n_rows <= PREP_SMALL_N)
         prep(k_prep<16>, 16);

@@ -308,12 +308,12 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
             if (e != hipSuccess) return hip_fail(c, e, "gradient clear");
         }
     }
-    ra.pending = fuse.adam.params ? fuse.adam.state + 2 : nullptr;
+    ra.fit_state = fuse.adam.params ? fuse.adam.state : nullptr;
     e = launch_raster_fwd(ra, st);
     ra.ev_start = ra.ev_stop = nullptr;
     ra.target = nullptr;  // the saved state is that of a plain forward
     ra.dparams = nullptr;
-    ra.pending = nullptr;
+    ra.fit_state = nullptr;
     if (e != hipSuccess) {
         // the appended counts were not consumed: clear them for the next forward
         (void)hipStreamSynchronize(st);

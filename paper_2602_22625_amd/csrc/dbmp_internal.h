@@ -100,7 +100,7 @@ template <> __device__ __forceinline__ float texel<uint16_t>(uint16_t v)
 // dbmp_fit_step): params non-null enables it.
 struct AdamArgs {
     float *params, *grad, *m, *v;
-    int *state;  // {updates applied, workgroups done, gradient pending, unused}
+    int *state;  // {updates applied, unused, gradient pending, unused}
     float lr, b1, b2, eps;
 };
 
@@ -159,7 +159,8 @@ struct RasterArgs {
     const int *order;                  // tiles by decreasing list length (SORTED, PERSISTENT)
     int *queue;                        // persistent work queues: fwd {head, done}, bwd {head, done}
     hipEvent_t ev_start, ev_stop;      // non-null: recorded by the device around the raster launch
-    int *pending;                      // fused fit step: set to 1 (a gradient awaits its update)
+    int *fit_state;                    // fused fit step: its Adam state (counts the update the
+                                       // binning applied; marks the new gradient pending)
     int n_cu;                          // compute units of the device (the walk form's choice)
 };
 

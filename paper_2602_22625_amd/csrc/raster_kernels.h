@@ -335,12 +335,19 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
              const int *__restrict__ order, int *__restrict__ queue,
              const float *__restrict__ target, float *__restrict__ loss_tile,
              float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
-             int *__restrict__ pending)
+             int *__restrict__ fit_state)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
     constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT, PIPE = LAUNCH == LAUNCH_TILE_PIPE;
     // a fit step's gradient now awaits its Adam update (applied by the next binning)
-    if (FUSED && pending && blockIdx.x == 0 && threadIdx.x == 0) *pending = 1;
+    // A fit step's Adam state {updates applied, unused, gradient pending, unused}: this step's
+    // binning applied the pending update if one was marked (count it), and this launch leaves a
+    // new gradient pending. One thread, after the binning has ended (stream order) and before
+    // the next step's binning reads the state.
+    if (FUSED && fit_state && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (fit_state[2]) fit_state[0] += 1;
+        fit_state[2] = 1;
+    }
     __shared__ __attribute__((aligned(16))) int s_ids[CAP + 4];
     __shared__ PrimRec s_rec[BATCH];
     __shared__ float s_loss[TS * TS / 64];
@@ -816,7 +823,7 @@ static void fwd_t(const RasterArgs &a, hipStream_t st)
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
         a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue, a.target,
         a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu),
-        a.pending);
+        a.fit_state);
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA, bool MSE, int LAUNCH>
