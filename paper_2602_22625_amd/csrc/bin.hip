@@ -228,6 +228,61 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
     // a fit step's pending Adam update (wave-uniform: every workgroup reads the same flag)
     const bool adam_on = adam.params && adam.state[2] != 0;
     const int t_adam = adam_on ? adam.state[0] + 1 : 0;
+    // The update of one parameter, as k_adam computes it (zero_grad). Its loads come before its
+    // stores (the buffers are distinct, but the compiler cannot know it, and would otherwise
+    // wait for each store).
+    auto adam_update = [&](long long at, float &p) {
+        const float gi = adam.grad[at], m0 = adam.m[at], v0 = adam.v[at];
+        const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
+        const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
+        const float mv = fmaf(adam.b1, m0, (1.f - adam.b1) * gi);
+        const float vv = fmaf(adam.b2, v0, (1.f - adam.b2) * gi * gi);
+        const float mhat = mv / c1, vhat = vv / c2;
+        p = p - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
+        adam.grad[at] = 0.f;
+        adam.m[at] = mv;
+        adam.v[at] = vv;
+        adam.params[at] = p;
+    };
+    // With 16 threads per primitive (small launches, where the workgroup's latency is the
+    // binning's), the parameter-wise work is spread over lanes before one lane per primitive
+    // assembles the record: one lane per parameter for the Adam update, one lane per float64
+    // exponential (and one for the sine and cosine). Every lane of a pass runs the same
+    // instructions, so the passes cost one evaluation each. The values are the same as those
+    // of the one-lane form.
+    constexpr bool SPLIT = PREP_PRIMS * 16 <= PREP_THREADS;
+    __shared__ float s_p[SPLIT ? PREP_PRIMS * 8 : 1];       // parameters after the update
+    __shared__ double s_e[SPLIT ? PREP_PRIMS * 12 : 1];     // exponentials, sine, cosine
+    if constexpr (SPLIT) {
+        const int pl = threadIdx.x >> 4, q = threadIdx.x & 15;
+        const long long gq = (long long)blockIdx.x * PREP_PRIMS + pl;
+        if (gq < n_rows && q < 8) {
+            float pq = params[gq * 8 + q];
+            if (adam_on) adam_update(gq * 8 + q, pq);
+            s_p[pl * 8 + q] = pq;
+        }
+        __syncthreads();
+        if (gq < n_rows) {
+            // lane q: s = exp(p2); 1/(1 + exp(-p4)) and 1/(1 + exp(p4)); 1/(1 + exp(-p5..7));
+            // exp(p5..7) (the colour derivative divides by 1 + exp(p)); lane 9: sin, cos of p3
+            const float *pp = s_p + pl * 8;
+            if (q < 9) {
+                const double x = q == 0 ? (double)pp[2]
+                               : q == 1 ? -(double)pp[4]
+                               : q == 2 ? (double)pp[4]
+                               : q < 6 ? -(double)pp[2 + q]
+                                       : (double)pp[q - 1];
+                const double e = exp(x);
+                s_e[pl * 12 + q] = (q == 0 || q >= 6) ? e : 1.0 / (1.0 + e);
+            } else if (q == 9) {
+                double st, ct;
+                sincos((double)pp[3], &st, &ct);
+                s_e[pl * 12 + 9] = st;
+                s_e[pl * 12 + 10] = ct;
+            }
+        }
+        __syncthreads();
+    }
     if (threadIdx.x < PREP_PRIMS) {
         const long long g = (long long)blockIdx.x * PREP_PRIMS + threadIdx.x;
         PrimRec rec;
@@ -243,20 +298,20 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
         rec.pad = 0;
         if (g < n_rows) {
             // Every load that does not wait on another is issued first, so that their latencies
-            // overlap: the parameters, the inputs of a pending Adam update (read whenever the
-            // update buffers are given; used only if it is pending), the image record, the
-            // bitmap index and the bitmap's box. The Adam stores come after all of them (the
-            // buffers are distinct, but the compiler cannot know it, and would otherwise wait
-            // for each store).
+            // overlap: in the one-lane form the parameters and the inputs of a pending Adam
+            // update (read whenever the update buffers are given; used only if it is pending),
+            // then the image record, the bitmap index and the bitmap's box.
             float p[8], gv[8], mv[8], vv[8];
+            if constexpr (!SPLIT) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
-            if (adam.params) {
+                for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
+                if (adam.params) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    gv[j] = adam.grad[g * 8 + j];
-                    mv[j] = adam.m[g * 8 + j];
-                    vv[j] = adam.v[g * 8 + j];
+                    for (int j = 0; j < 8; ++j) {
+                        gv[j] = adam.grad[g * 8 + j];
+                        mv[j] = adam.m[g * 8 + j];
+                        vv[j] = adam.v[g * 8 + j];
+                    }
                 }
             }
             const int b = find_by_prim(imgs, n_images, g);
@@ -271,24 +326,45 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
                 ylo = box[4 * kb + 2];
                 yhi = box[4 * kb + 3];
             }
-            if (adam_on) {
-                // the previous step's update of this row, as k_adam computes it (zero_grad)
-                const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
-                const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
+            // s = exp(p2); sin, cos of p3; the sigmoid of the opacity logit and its complement;
+            // the colour sigmoids and exp of the colour logits
+            double s, st, ct, sig, omsig, c3[3], ep[3];
+            if constexpr (SPLIT) {
+                const double *e = s_e + threadIdx.x * 12;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const float gi = gv[j];
-                    mv[j] = fmaf(adam.b1, mv[j], (1.f - adam.b1) * gi);
-                    vv[j] = fmaf(adam.b2, vv[j], (1.f - adam.b2) * gi * gi);
-                    const float mhat = mv[j] / c1, vhat = vv[j] / c2;
-                    p[j] = p[j] - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
+                for (int j = 0; j < 8; ++j) p[j] = s_p[threadIdx.x * 8 + j];
+                s = e[0]; sig = e[1]; omsig = e[2];
+                c3[0] = e[3]; c3[1] = e[4]; c3[2] = e[5];
+                ep[0] = e[6]; ep[1] = e[7]; ep[2] = e[8];
+                st = e[9]; ct = e[10];
+            } else {
+                if (adam_on) {  // the same arithmetic as adam_update, every store after the loads
+                    const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
+                    const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float gi = gv[j];
+                        mv[j] = fmaf(adam.b1, mv[j], (1.f - adam.b1) * gi);
+                        vv[j] = fmaf(adam.b2, vv[j], (1.f - adam.b2) * gi * gi);
+                        const float mhat = mv[j] / c1, vhat = vv[j] / c2;
+                        p[j] = p[j] - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        adam.grad[g * 8 + j] = 0.f;
+                        adam.m[g * 8 + j] = mv[j];
+                        adam.v[g * 8 + j] = vv[j];
+                        adam.params[g * 8 + j] = p[j];
+                    }
                 }
+                s = exp((double)p[2]);
+                sincos((double)p[3], &st, &ct);
+                sig = 1.0 / (1.0 + exp(-(double)p[4]));
+                omsig = 1.0 / (1.0 + exp((double)p[4]));
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    adam.grad[g * 8 + j] = 0.f;
-                    adam.m[g * 8 + j] = mv[j];
-                    adam.v[g * 8 + j] = vv[j];
-                    adam.params[g * 8 + j] = p[j];
+                for (int j = 0; j < 3; ++j) {
+                    c3[j] = 1.0 / (1.0 + exp(-(double)p[5 + j]));
+                    ep[j] = exp((double)p[5 + j]);
                 }
             }
             rec.img = b; rec.tile_off = D.tile_off; rec.ntx = D.ntx; rec.W = D.W; rec.H = D.H;
@@ -301,15 +377,12 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
                 bool fin = true;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) fin = fin && isfinite(p[j]);
-                const double s = exp((double)p[2]);
                 if (!(s > 0.0) || !isfinite(s)) fin = false;  // scale underflows or overflows
                 if (!fin) {
                     atomicOr(&flags[F_S_NONFINITE], 1);
                     ok = false;
                 }
                 if (ok) {
-                    double st, ct;
-                    sincos((double)p[3], &st, &ct);
                     const double inv_s = 1.0 / s;
                     const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1);  // dU/du, dV/dv
                     const double x = p[0], y = p[1];
@@ -321,17 +394,12 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
                     rec.eV = (cv + 1.0) - rec.aV * x - rec.bV * y;
                     rec.faU = (float)rec.aU; rec.fbU = (float)rec.bU;
                     rec.faV = (float)rec.aV; rec.fbV = (float)rec.bV;
-                    const double sig = 1.0 / (1.0 + exp(-(double)p[4]));
-                    const double omsig = 1.0 / (1.0 + exp((double)p[4]));  // 1 - sigmoid
                     rec.ka = (float)(alpha_max * sig);
                     rec.kaom = (float)(alpha_max * sig * omsig);
-                    double c3[3];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) c3[j] = 1.0 / (1.0 + exp(-(double)p[5 + j]));
                     rec.cr = (float)c3[0]; rec.cg = (float)c3[1]; rec.cb = (float)c3[2];
-                    rec.ccr = (float)(c3[0] / (1.0 + exp((double)p[5])));  // c (1 - c)
-                    rec.ccg = (float)(c3[1] / (1.0 + exp((double)p[6])));
-                    rec.ccb = (float)(c3[2] / (1.0 + exp((double)p[7])));
+                    rec.ccr = (float)(c3[0] / (1.0 + ep[0]));  // c (1 - c)
+                    rec.ccg = (float)(c3[1] / (1.0 + ep[1]));
+                    rec.ccb = (float)(c3[2] / (1.0 + ep[2]));
                     const int Hp = Hb + 2;
                     rec.tex = k * Hp * Wp;
                     if (xlo == INT_MIN) {  // the bitmap holds a non-finite texel (read as 0)
