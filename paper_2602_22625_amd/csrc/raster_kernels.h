@@ -700,25 +700,19 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
         // every wave has added its partials: one global atomic per (entry, parameter) per tile
         __syncthreads();
         for (int t = threadIdx.x; t < cnt * 8; t += NT) {
+            // an entry's 8 slots lie in one wave, whose lanes read s0, s1 and their own slot
+            // before any lane clears its slot (one instruction stream); then one atomic per lane
             const int q = t & 7;
-            if (q == 1) continue;  // written by the thread of parameter 0
             const PrimRec &r = s_rec[t >> 3];
-            float *dst = dparams + (size_t)r.id * 8 + q;
-            const float v = s_grad[t];
+            const float s0 = s_grad[t & ~7], s1 = s_grad[(t & ~7) + 1], v = s_grad[t];
+            float x;
+            if (q < 2)
+                x = -r.ka * fmaf(q == 0 ? r.faU : r.fbU, s0, (q == 0 ? r.faV : r.fbV) * s1);
+            else
+                x = (q == 2 ? -r.ka : q == 3 ? r.ka : q == 4 ? r.kaom : q == 5 ? r.ccr
+                     : q == 6 ? r.ccg : r.ccb) * v;
             s_grad[t] = 0.f;  // ready for the next batch
-            if (q == 0) {
-                const float w = s_grad[t + 1];
-                s_grad[t + 1] = 0.f;
-                const float gx = -r.ka * fmaf(r.faU, v, r.faV * w);
-                const float gy = -r.ka * fmaf(r.fbU, v, r.fbV * w);
-                if (gx != 0.f) unsafeAtomicAdd(dst, gx);
-                if (gy != 0.f) unsafeAtomicAdd(dst + 1, gy);
-            } else {
-                const float f = q == 2 ? -r.ka : q == 3 ? r.ka : q == 4 ? r.kaom
-                              : q == 5 ? r.ccr : q == 6 ? r.ccg : r.ccb;
-                const float x = f * v;
-                if (x != 0.f) unsafeAtomicAdd(dst, x);
-            }
+            if (x != 0.f) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + q, x);
         }
     }
 }
