@@ -114,7 +114,7 @@ __device__ __forceinline__ bool tile_hits(const R &r, int X0, int X1, int Y0, in
 // down, then a scatter. Ties are placed in any order: every tile is computed independently, so
 // the order changes no image bit. Run by NTH threads of one workgroup: by an extra workgroup of
 // k_prep on the previous forward's lengths (small canvases: no launch of its own, and off the
-// critical path), else by k_order after the binning.
+// critical path), else by the many-workgroup form below after the binning.
 // ------------------------------------------------------------------------------------------
 constexpr int ORDER_BINS = 1024;
 constexpr int ORDER_IN_PREP_MAX = 4096;  // tiles up to which the binning orders them
@@ -182,12 +182,92 @@ __device__ __forceinline__ void order_tiles(const int *__restrict__ tile_count, 
     }
 }
 
-__global__ void __launch_bounds__(ORDER_BINS)
-k_order(const int *__restrict__ tile_count, int n_tiles, int *__restrict__ order)
+// Many tiles (beyond the binning's own ordering): the same counting sort spread over
+// workgroups of ORDER_CHUNK tiles, so that no single compute unit takes every tile's LDS atomic
+// (most tiles fall into a few length bins, whose same-address atomics serialise). Three
+// launches: per-workgroup histograms (hist[group * ORDER_BINS + bin]); one exclusive scan over
+// them in bin-major order, longest bin first; then each workgroup places its tiles at its
+// offsets.
+constexpr int ORDER_CHUNK = 2048;
+constexpr int ORDER_THREADS = 256;
+
+size_t order_hist_bytes(long long n_tiles)
+{
+    return 4 * (size_t)ORDER_BINS * (size_t)((n_tiles + ORDER_CHUNK - 1) / ORDER_CHUNK);
+}
+
+__device__ __forceinline__ int order_bin(int len)
+{
+    return ORDER_BINS - 1 - min(max(len, 0), ORDER_BINS - 1);  // bin 0: the longest lists
+}
+
+__global__ void __launch_bounds__(ORDER_THREADS)
+k_order_count(const int *__restrict__ tile_count, int n_tiles, int *__restrict__ ghist)
 {
     __shared__ int hist[ORDER_BINS];
+    const int t0 = blockIdx.x * ORDER_CHUNK;
+    for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS) hist[b] = 0;
+    __syncthreads();
+    for (int i = t0 + threadIdx.x; i < min(t0 + ORDER_CHUNK, n_tiles); i += ORDER_THREADS)
+        atomicAdd(&hist[order_bin(tile_count[i])], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS)
+        ghist[(size_t)blockIdx.x * ORDER_BINS + b] = hist[b];
+}
+
+// One workgroup of ORDER_BINS threads: thread b owns bin b's counts of the G groups (a wave reads
+// one group's consecutive bins), takes their total, adds the exclusive sum of the earlier bins
+// (wave scans of the totals), and writes its groups' offsets. The counts are read ORDER_IN_FLIGHT
+// at a time, so their loads overlap.
+constexpr int ORDER_IN_FLIGHT = 32;
+
+__global__ void __launch_bounds__(ORDER_BINS) k_order_scan(int *__restrict__ ghist, int G)
+{
     __shared__ int wsum[ORDER_BINS / 64];
-    order_tiles<ORDER_BINS, false>(tile_count, n_tiles, order, hist, wsum);
+    const int b = threadIdx.x, lane = b & 63;
+    int sum = 0;
+    for (int g0 = 0; g0 < G; g0 += ORDER_IN_FLIGHT) {
+        int v[ORDER_IN_FLIGHT];
+#pragma unroll
+        for (int k = 0; k < ORDER_IN_FLIGHT; ++k)
+            v[k] = g0 + k < G ? ghist[(size_t)(g0 + k) * ORDER_BINS + b] : 0;
+#pragma unroll
+        for (int k = 0; k < ORDER_IN_FLIGHT; ++k) sum += v[k];
+    }
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[b >> 6] = x;
+    __syncthreads();
+    int run = x - sum;
+    for (int w = 0; w < (b >> 6); ++w) run += wsum[w];
+    for (int g0 = 0; g0 < G; g0 += ORDER_IN_FLIGHT) {
+        int v[ORDER_IN_FLIGHT];
+#pragma unroll
+        for (int k = 0; k < ORDER_IN_FLIGHT; ++k)
+            v[k] = g0 + k < G ? ghist[(size_t)(g0 + k) * ORDER_BINS + b] : 0;
+#pragma unroll
+        for (int k = 0; k < ORDER_IN_FLIGHT; ++k) {
+            if (g0 + k < G) ghist[(size_t)(g0 + k) * ORDER_BINS + b] = run;
+            run += v[k];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(ORDER_THREADS)
+k_order_place(const int *__restrict__ tile_count, int n_tiles, const int *__restrict__ ghist,
+              int *__restrict__ order)
+{
+    __shared__ int pos[ORDER_BINS];
+    const int t0 = blockIdx.x * ORDER_CHUNK;
+    for (int b = threadIdx.x; b < ORDER_BINS; b += ORDER_THREADS)
+        pos[b] = ghist[(size_t)blockIdx.x * ORDER_BINS + b];
+    __syncthreads();
+    for (int i = t0 + threadIdx.x; i < min(t0 + ORDER_CHUNK, n_tiles); i += ORDER_THREADS)
+        order[atomicAdd(&pos[order_bin(tile_count[i])], 1)] = i;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -497,7 +577,8 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
                                                               a.box);
     }
     // small canvases: one extra binning workgroup orders the tiles by the previous forward's
-    // list lengths, off the critical path; larger ones: k_order on this forward's lengths
+    // list lengths, off the critical path; larger ones: the many-workgroup ordering of this
+    // forward's lengths
     const bool order_in_prep = a.order && a.n_tiles <= ORDER_IN_PREP_MAX;
     auto prep = [&](auto kern, int pp) {
         const long long n_prep = (a.n_rows + pp - 1) / pp;
@@ -512,8 +593,13 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
         prep(k_prep<16>, 16);
     else
         prep(k_prep<64>, 64);
-    if (a.order && !order_in_prep && a.n_tiles > 0)
-        k_order<<<1, ORDER_BINS, 0, st>>>(a.tile_count, a.n_tiles, a.order);
+    if (a.order && !order_in_prep && a.n_tiles > 0) {
+        const int G = (a.n_tiles + ORDER_CHUNK - 1) / ORDER_CHUNK;
+        k_order_count<<<G, ORDER_THREADS, 0, st>>>(a.tile_count, a.n_tiles, a.order_hist);
+        k_order_scan<<<1, ORDER_BINS, 0, st>>>(a.order_hist, G);
+        k_order_place<<<G, ORDER_THREADS, 0, st>>>(a.tile_count, a.n_tiles, a.order_hist,
+                                                     a.order);
+    }
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ struct dbmp_ctx {
     int device = 0;
     std::string err;
     Buf recs, tile_count, tile_len, lists, saveK, saveT, atlas_pad, box, imgs, flags, counter,
-        list_max, loss_tile, order, queue;
+        list_max, loss_tile, order, order_hist, queue;
     int list_cap = 0;  // entries per tile list
     // launch schedule of the raster kernels (dbmp_set_schedule)
     int sched = SCHED_GRID;
@@ -248,7 +248,8 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     if ((rc = ensure(c, c->saveK, 4 * (size_t)n_pix, st, "saveK"))) return rc;
     if ((rc = ensure(c, c->saveT, 4 * (size_t)n_pix, st, "saveT"))) return rc;
     if (c->sched != SCHED_GRID &&
-        (rc = ensure(c, c->order, 4 * (size_t)tiles, st, "tile order")))
+        ((rc = ensure(c, c->order, 4 * (size_t)tiles, st, "tile order")) ||
+         (rc = ensure(c, c->order_hist, order_hist_bytes(tiles), st, "tile order counts"))))
         return rc;
     if (c->imgs.cap < sizeof(ImgDev) * ni || !same_imgs(imgs, c->imgs_uploaded)) {
         if (capturing(st))
@@ -272,6 +273,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ba.tile_count = (int *)c->tile_count.p; ba.lists = (int *)c->lists.p;
     ba.list_cap = c->list_cap; ba.flags = (int *)c->flags.p; ba.pad_atlas = false;
     ba.order = c->sched != SCHED_GRID ? (int *)c->order.p : nullptr;
+    ba.order_hist = (int *)c->order_hist.p;
     ba.adam = fuse.adam;
     ba.prev_len = (const int *)c->tile_len.p;
     hipError_t e = launch_binning(ba, st);
@@ -369,7 +371,7 @@ int dbmp_destroy(dbmp_ctx *c)
         (void)hipDeviceSynchronize();
         Buf *bs[] = {&c->recs, &c->tile_count, &c->tile_len, &c->lists, &c->saveK, &c->saveT,
                      &c->atlas_pad, &c->box, &c->imgs, &c->flags, &c->counter, &c->list_max,
-                     &c->loss_tile, &c->order, &c->queue};
+                     &c->loss_tile, &c->order, &c->order_hist, &c->queue};
         for (Buf *b : bs)
             if (b->p) (void)hipFree(b->p);
     }

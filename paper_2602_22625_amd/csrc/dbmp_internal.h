@@ -126,6 +126,7 @@ struct BinArgs {
     bool pad_atlas;    // pad the atlas and find its boxes (false: reuse the stored ones)
     AdamArgs adam;     // adam.params non-null: apply the pending Adam update first
     int *order;        // non-null: tiles by decreasing list length are written here
+    int *order_hist;   // ORDER_BINS x ceil(n_tiles / ORDER_CHUNK) ints (many-tile ordering)
     const int *prev_len;  // the previous forward's list lengths (any values: only the order uses them)
 };
 
@@ -171,6 +172,8 @@ struct RasterArgs {
 //                     device queue until it is empty (or, with grab = 0, in fixed strides).
 enum { SCHED_GRID = 0, SCHED_SORTED = 1, SCHED_PERSISTENT = 2 };
 
+// workspace of the many-tile ordering (bin.hip): per-workgroup histograms of the list lengths
+size_t order_hist_bytes(long long n_tiles);
 hipError_t launch_binning(const BinArgs &a, hipStream_t st);
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);

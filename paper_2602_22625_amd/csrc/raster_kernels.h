@@ -323,6 +323,20 @@ __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__r
 // loss against `target` (the image, the per-pixel (K, T_K) and, for a list of at most 64
 // entries, the staged records are still on chip); the gradient is added to dparams and the
 // tile's squared error written to loss_tile.
+// The backward's walk over a tile's sorted list (defined below, after the forward kernel that
+// also runs it in the fused fit step).
+template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, typename IdAt>
+__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
+                                         PrimRec *__restrict__ s_rec,
+                                         float *__restrict__ s_grad,
+                                         const PrimRec *__restrict__ recs,
+                                         const TexT *__restrict__ atlas, int Wp,
+                                         const TileGeom<TS> &tg, uint64_t vmask, float g0,
+                                         float g1, float g2, float ga, float G0, float G1,
+                                         float G2, int K, float TK, float *__restrict__ dparams,
+                                         double cu1, double cv1, float cu_cv, float cv_cu,
+                                         int lane);
+
 template <int TS, typename TexT, bool BG_PP, bool FUSED, int LAUNCH>
 __global__ void __launch_bounds__(TS * TS)
 k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
