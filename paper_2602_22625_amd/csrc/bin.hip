@@ -308,57 +308,103 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
     // a fit step's pending Adam update (wave-uniform: every workgroup reads the same flag)
     const bool adam_on = adam.params && adam.state[2] != 0;
     const int t_adam = adam_on ? adam.state[0] + 1 : 0;
-    // The update of one parameter, as k_adam computes it (zero_grad). Its loads come before its
-    // stores (the buffers are distinct, but the compiler cannot know it, and would otherwise
-    // wait for each store).
-    auto adam_update = [&](long long at, float &p) {
-        const float gi = adam.grad[at], m0 = adam.m[at], v0 = adam.v[at];
-        const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
-        const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
-        const float mv = fmaf(adam.b1, m0, (1.f - adam.b1) * gi);
-        const float vv = fmaf(adam.b2, v0, (1.f - adam.b2) * gi * gi);
-        const float mhat = mv / c1, vhat = vv / c2;
-        p = p - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
-        adam.grad[at] = 0.f;
-        adam.m[at] = mv;
-        adam.v[at] = vv;
-        adam.params[at] = p;
-    };
-    // With 16 threads per primitive (small launches, where the workgroup's latency is the
-    // binning's), the parameter-wise work is spread over lanes before one lane per primitive
-    // assembles the record: one lane per parameter for the Adam update, one lane per float64
-    // exponential (and one for the sine and cosine). Every lane of a pass runs the same
-    // instructions, so the passes cost one evaluation each. The values are the same as those
-    // of the one-lane form.
-    constexpr bool SPLIT = PREP_PRIMS * 16 <= PREP_THREADS;
-    __shared__ float s_p[SPLIT ? PREP_PRIMS * 8 : 1];       // parameters after the update
-    __shared__ double s_e[SPLIT ? PREP_PRIMS * 12 : 1];     // exponentials, sine, cosine
-    if constexpr (SPLIT) {
-        const int pl = threadIdx.x >> 4, q = threadIdx.x & 15;
+    // The parameter-wise work is spread over the LANES = PREP_THREADS / PREP_PRIMS lanes of each
+    // primitive (16 or 4) before one lane per primitive assembles the record: the lanes take the
+    // 8 parameters' Adam updates in turn, then the 9 float64 exponentials and the sine and
+    // cosine. Every lane of a pass runs the same instructions, so a pass costs one evaluation,
+    // and a wave's loads of parameters and moments are coalesced. The values are those of a
+    // one-lane evaluation; the update is k_adam's (zero_grad), bit for bit.
+    // The record lane's image record, bitmap index and bitmap box, requested before the
+    // parameter-wise passes so that their latency overlaps them.
+    const long long g_rec = (long long)blockIdx.x * PREP_PRIMS + threadIdx.x;
+    int b = 0, k = 0, xlo = 0, xhi = -1, ylo = 0, yhi = -1;
+    bool k_ok = false;
+    ImgDev D{};
+    if (threadIdx.x < PREP_PRIMS && g_rec < n_rows) {
+        b = find_by_prim(imgs, n_images, g_rec);
+        D = imgs[b];
+        k = idx[g_rec];
+        k_ok = k >= 0 && k < B;
+        if (k_ok) {
+            xlo = box[4 * k];
+            xhi = box[4 * k + 1];
+            ylo = box[4 * k + 2];
+            yhi = box[4 * k + 3];
+        }
+    }
+    constexpr int LANES = PREP_THREADS / PREP_PRIMS;
+    constexpr int PPL = (8 + LANES - 1) / LANES;  // parameters per lane
+    static_assert(LANES >= 4 && PREP_THREADS % PREP_PRIMS == 0, "lanes per primitive");
+    __shared__ float s_p[PREP_PRIMS * 8];     // parameters after the update
+    __shared__ double s_e[PREP_PRIMS * 12];   // exponentials, sine, cosine
+    {
+        const int pl = threadIdx.x / LANES, l = threadIdx.x % LANES;
         const long long gq = (long long)blockIdx.x * PREP_PRIMS + pl;
-        if (gq < n_rows && q < 8) {
-            float pq = params[gq * 8 + q];
-            if (adam_on) adam_update(gq * 8 + q, pq);
-            s_p[pl * 8 + q] = pq;
+        // all loads first, then the arithmetic, then the stores (the buffers are distinct, but
+        // the compiler cannot know it, and would otherwise wait for each store)
+        float pq[PPL], gv[PPL], mv[PPL], vv[PPL];
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int q = l + k * LANES;
+            if (gq < n_rows && q < 8) {
+                pq[k] = params[gq * 8 + q];
+                if (adam_on) {
+                    gv[k] = adam.grad[gq * 8 + q];
+                    mv[k] = adam.m[gq * 8 + q];
+                    vv[k] = adam.v[gq * 8 + q];
+                }
+            }
+        }
+        if (adam_on) {
+            const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
+            const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const int q = l + k * LANES;
+                if (gq < n_rows && q < 8) {
+                    const float gi = gv[k];
+                    mv[k] = fmaf(adam.b1, mv[k], (1.f - adam.b1) * gi);
+                    vv[k] = fmaf(adam.b2, vv[k], (1.f - adam.b2) * gi * gi);
+                    const float mhat = mv[k] / c1, vhat = vv[k] / c2;
+                    pq[k] = pq[k] - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                const int q = l + k * LANES;
+                if (gq < n_rows && q < 8) {
+                    adam.grad[gq * 8 + q] = 0.f;
+                    adam.m[gq * 8 + q] = mv[k];
+                    adam.v[gq * 8 + q] = vv[k];
+                    adam.params[gq * 8 + q] = pq[k];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int q = l + k * LANES;
+            if (gq < n_rows && q < 8) s_p[pl * 8 + q] = pq[k];
         }
         __syncthreads();
         if (gq < n_rows) {
-            // lane q: s = exp(p2); 1/(1 + exp(-p4)) and 1/(1 + exp(p4)); 1/(1 + exp(-p5..7));
-            // exp(p5..7) (the colour derivative divides by 1 + exp(p)); lane 9: sin, cos of p3
+            // item q: s = exp(p2); 1/(1 + exp(-p4)) and 1/(1 + exp(p4)); 1/(1 + exp(-p5..7));
+            // exp(p5..7) (the colour derivative divides by 1 + exp(p)); item 9: sin, cos of p3
             const float *pp = s_p + pl * 8;
-            if (q < 9) {
-                const double x = q == 0 ? (double)pp[2]
-                               : q == 1 ? -(double)pp[4]
-                               : q == 2 ? (double)pp[4]
-                               : q < 6 ? -(double)pp[2 + q]
-                                       : (double)pp[q - 1];
-                const double e = exp(x);
-                s_e[pl * 12 + q] = (q == 0 || q >= 6) ? e : 1.0 / (1.0 + e);
-            } else if (q == 9) {
-                double st, ct;
-                sincos((double)pp[3], &st, &ct);
-                s_e[pl * 12 + 9] = st;
-                s_e[pl * 12 + 10] = ct;
+            for (int q = l; q < 10; q += LANES) {
+                if (q < 9) {
+                    const double x = q == 0 ? (double)pp[2]
+                                   : q == 1 ? -(double)pp[4]
+                                   : q == 2 ? (double)pp[4]
+                                   : q < 6 ? -(double)pp[2 + q]
+                                           : (double)pp[q - 1];
+                    const double e = exp(x);
+                    s_e[pl * 12 + q] = (q == 0 || q >= 6) ? e : 1.0 / (1.0 + e);
+                } else {
+                    double st, ct;
+                    sincos((double)pp[3], &st, &ct);
+                    s_e[pl * 12 + 9] = st;
+                    s_e[pl * 12 + 10] = ct;
+                }
             }
         }
         __syncthreads();
@@ -377,76 +423,14 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
         rec.id = (int)g;
         rec.pad = 0;
         if (g < n_rows) {
-            // Every load that does not wait on another is issued first, so that their latencies
-            // overlap: in the one-lane form the parameters and the inputs of a pending Adam
-            // update (read whenever the update buffers are given; used only if it is pending),
-            // then the image record, the bitmap index and the bitmap's box.
-            float p[8], gv[8], mv[8], vv[8];
-            if constexpr (!SPLIT) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) p[j] = params[g * 8 + j];
-                if (adam.params) {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        gv[j] = adam.grad[g * 8 + j];
-                        mv[j] = adam.m[g * 8 + j];
-                        vv[j] = adam.v[g * 8 + j];
-                    }
-                }
-            }
-            const int b = find_by_prim(imgs, n_images, g);
-            const ImgDev D = imgs[b];
-            const int k = idx[g];
-            const bool k_ok = k >= 0 && k < B;
-            const int kb = k_ok ? k : 0;
-            int xlo = 0, xhi = -1, ylo = 0, yhi = -1;
-            if (k_ok) {
-                xlo = box[4 * kb];
-                xhi = box[4 * kb + 1];
-                ylo = box[4 * kb + 2];
-                yhi = box[4 * kb + 3];
-            }
             // s = exp(p2); sin, cos of p3; the sigmoid of the opacity logit and its complement;
             // the colour sigmoids and exp of the colour logits
-            double s, st, ct, sig, omsig, c3[3], ep[3];
-            if constexpr (SPLIT) {
-                const double *e = s_e + threadIdx.x * 12;
+            float p[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) p[j] = s_p[threadIdx.x * 8 + j];
-                s = e[0]; sig = e[1]; omsig = e[2];
-                c3[0] = e[3]; c3[1] = e[4]; c3[2] = e[5];
-                ep[0] = e[6]; ep[1] = e[7]; ep[2] = e[8];
-                st = e[9]; ct = e[10];
-            } else {
-                if (adam_on) {  // the same arithmetic as adam_update, every store after the loads
-                    const float c1 = (float)(1.0 - pow((double)adam.b1, (double)t_adam));
-                    const float c2 = (float)(1.0 - pow((double)adam.b2, (double)t_adam));
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const float gi = gv[j];
-                        mv[j] = fmaf(adam.b1, mv[j], (1.f - adam.b1) * gi);
-                        vv[j] = fmaf(adam.b2, vv[j], (1.f - adam.b2) * gi * gi);
-                        const float mhat = mv[j] / c1, vhat = vv[j] / c2;
-                        p[j] = p[j] - adam.lr * mhat / (sqrtf(vhat) + adam.eps);
-                    }
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        adam.grad[g * 8 + j] = 0.f;
-                        adam.m[g * 8 + j] = mv[j];
-                        adam.v[g * 8 + j] = vv[j];
-                        adam.params[g * 8 + j] = p[j];
-                    }
-                }
-                s = exp((double)p[2]);
-                sincos((double)p[3], &st, &ct);
-                sig = 1.0 / (1.0 + exp(-(double)p[4]));
-                omsig = 1.0 / (1.0 + exp((double)p[4]));
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    c3[j] = 1.0 / (1.0 + exp(-(double)p[5 + j]));
-                    ep[j] = exp((double)p[5 + j]);
-                }
-            }
+            for (int j = 0; j < 8; ++j) p[j] = s_p[threadIdx.x * 8 + j];
+            const double *e = s_e + threadIdx.x * 12;
+            const double s = e[0], sig = e[1], omsig = e[2], st = e[9], ct = e[10];
+            const double c3[3] = {e[3], e[4], e[5]}, ep[3] = {e[6], e[7], e[8]};
             rec.img = b; rec.tile_off = D.tile_off; rec.ntx = D.ntx; rec.W = D.W; rec.H = D.H;
             if (g >= D.prim_off && g < D.prim_off + D.N) {
                 bool ok = true;
