@@ -27,10 +27,14 @@
 //     dL/dnu_j    = dL/dalpha_j alpha_max sigma (1 - sigma) M
 //     dL/dU', dL/dV' = dL/dalpha_j alpha_max sigma (dM/dU, dM/dV), then through Eq. (1)-(2) to
 //     x, y, log s, theta (Eq. 7).
-// The 8 per-lane partials are reduced across the wave by a transposed butterfly built from
+// The 8 per-lane factors are reduced across the wave by a transposed butterfly built from
 // gfx950's cross-row lane swaps (v_permlane32_swap, v_permlane16_swap) and DPP row/quad
-// permutes, after which lane 8q holds the wave total of parameter q; eight lanes then issue
-// one float32 atomic each per (wave, primitive).
+// permutes, after which lane 8q holds the wave total of factor q; eight lanes add them into the
+// workgroup's per-entry LDS sums, which after each batch are scaled by the primitive's constant
+// factors and flushed with one float32 atomic per (tile entry, parameter).
+//
+// Each walk comes in two builds (LAUNCH below): one texel cell in flight, or two, where the
+// next visited entry's texels are requested before the current entry is processed.
 #pragma once
 
 #include "dbmp_internal.h"
