@@ -348,7 +348,9 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
             const int q = l + k * LANES;
             if (gq < n_rows && q < 8) {
                 pq[k] = params[gq * 8 + q];
-                if (adam_on) {
+                // read whenever the update buffers are given, used only if an update is
+                // pending: the loads then overlap the load of the pending flag
+                if (adam.params) {
                     gv[k] = adam.grad[gq * 8 + q];
                     mv[k] = adam.m[gq * 8 + q];
                     vv[k] = adam.v[gq * 8 + q];
