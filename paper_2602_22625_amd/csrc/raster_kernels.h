@@ -384,6 +384,20 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         }
         if (n > list_cap) return;  // this tile's list did not fit (reported by dbmp_check)
         const TileGeom<TS> tg = tile_geom<TS>(tile, imgs, n_images);
+        // the fused step's target pixel, requested now so that its latency passes during the
+        // walks (it is used after the forward, to form dL/dI)
+        float tq0 = 0.f, tq1 = 0.f, tq2 = 0.f;
+        if (FUSED && tg.valid) {
+            using GFloat = const __attribute__((address_space(1))) float;
+            GFloat *tgt = (GFloat *)target;
+            asm volatile("" : "+s"(tgt));  // an ordinary pointer: the loads stay here
+            const size_t tplane = (size_t)tg.D.H * tg.D.W;
+            GFloat *tp = tgt + 3 * tg.D.pix_off + tg.pix;
+            tq0 = tp[0];
+            tq1 = tp[tplane];
+            tq2 = tp[2 * tplane];
+            asm volatile("" ::: "memory");
+        }
         int *seg = lists + (size_t)tile * list_cap;
         const bool in_lds = n <= CAP;
 
@@ -544,8 +558,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         // dL/dI of the image's MSE, formed as the separate MSE backward forms it
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, sq = 0.f;
         if (tg.valid) {
-            const float *tp = target + 3 * D.pix_off + tg.pix;
-            const float e0 = I0 - tp[0], e1 = I1 - tp[plane], e2 = I2 - tp[2 * plane];
+            const float e0 = I0 - tq0, e1 = I1 - tq1, e2 = I2 - tq2;
             sq = fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
             const float sc = 2.f / (3.f * (float)plane);
             g0 = sc * e0; g1 = sc * e1; g2 = sc * e2;
