@@ -460,6 +460,83 @@ def test_pipelined_and_single_cell_walks_agree():
             assert np.all(np.abs(x1 - x2) <= 1e-5 * scale), (bf16, tile)
 
 
+def _long_and_deep_scenes():
+    """The scenes of the deep-stack and long-list tests: 400 layers with opaque ones over a 48 x 48
+    canvas, and 3,000 primitives over 64 x 64 (lists beyond the LDS sort capacity)."""
+    g = np.random.default_rng(9)
+    solid = np.ones((1, 16, 16), dtype=np.float32)
+    disk = synth.soft_disk(32)[::2, ::2][None].astype(np.float32)
+    atlas = np.concatenate([solid, disk, np.zeros_like(solid)]).astype(np.float32)
+    N = 400
+    deep = np.zeros((N, 8), dtype=np.float32)
+    deep[:, 0] = g.uniform(16, 32, N)
+    deep[:, 1] = g.uniform(16, 32, N)
+    deep[:, 2] = np.log(g.uniform(6, 12, N))
+    deep[:, 3] = g.uniform(0, 2 * np.pi, N)
+    deep[:, 4] = g.normal(1.0, 2.0, N)
+    deep[:, 5:] = g.normal(0, 1, (N, 3))
+    deep[::37, 4] = 40.0
+    idx = g.integers(0, 2, N).astype(np.int32)
+    idx[::37] = 0
+    idx[5] = 2
+    yield "deep", 48, deep, idx, atlas, (0.3, 0.2, 0.1)
+    g = np.random.default_rng(10)
+    N = 3000
+    lng = np.zeros((N, 8), dtype=np.float32)
+    lng[:, 0] = g.uniform(0, 64, N)
+    lng[:, 1] = g.uniform(0, 64, N)
+    lng[:, 2] = np.log(g.uniform(8, 30, N))
+    lng[:, 3] = g.uniform(0, 6.28, N)
+    lng[:, 4] = g.normal(-4, 1, N)
+    lng[:, 5:] = g.normal(0, 1, (N, 3))
+    yield "long", 64, lng, np.zeros(N, dtype=np.int32), synth.soft_disk(32)[None], (1, 1, 1)
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_walk_builds_agree_on_deep_and_long_lists(tile):
+    """The deep-stack and long-list scenes rendered alone (a launch of few waves: the pipelined
+    walks) and as the first image of a batch with a 1024 x 1024 canvas (the one-cell walks), over
+    several batches of staged records and the LDS and global-memory sort paths: images bitwise
+    equal; the backward with dL/dI and dL/dA on the first image only, within 1e-5 of each
+    column's scale."""
+    from paper_2602_22625_amd.render import Renderer
+    dev = torch.device("cuda")
+    for name, S, params, idx, atlas, bg in _long_and_deep_scenes():
+        N = params.shape[0]
+        p = torch.tensor(params, device=dev)
+        i_t = torch.tensor(idx, device=dev)
+        a = torch.tensor(atlas, device=dev)
+        bg1 = torch.tensor(np.asarray(bg, dtype=np.float32), device=dev)
+        R1, R2 = Renderer(), Renderer()
+        i1, a1 = R1.render(p, i_t, a, S, S, bg1, 1.0, tile)
+        descs = [(S, S, N, 0, 0), (1024, 1024, N, N, S * S)]
+        P2 = torch.cat([p, p]).contiguous()
+        I2 = torch.cat([i_t, i_t]).contiguous()
+        i2, a2 = R2.render_batched(descs, P2, I2, a, torch.stack([bg1, bg1]).contiguous(), 1.0,
+                                   tile)
+        torch.cuda.synchronize()
+        R1.check()
+        R2.check()
+        assert torch.equal(i1.reshape(-1), i2[:3 * S * S]), (name, tile)
+        assert torch.equal(a1.reshape(-1), a2[:S * S]), (name, tile)
+        g = np.random.default_rng(11)
+        gI = g.standard_normal((3, S, S)).astype(np.float32)
+        gA = g.standard_normal((S, S)).astype(np.float32)
+        gI2 = torch.zeros(3 * (S * S + 1024 * 1024), device=dev)
+        gI2[:3 * S * S] = torch.tensor(gI.reshape(-1), device=dev)
+        gA2 = torch.zeros(S * S + 1024 * 1024, device=dev)
+        gA2[:S * S] = torch.tensor(gA.reshape(-1), device=dev)
+        g1 = R1.backward(torch.tensor(gI, device=dev), torch.tensor(gA, device=dev), n_params=N)
+        g2 = R2.backward(gI2, gA2, n_params=2 * N)
+        R1.check()
+        R2.check()
+        x1 = g1.cpu().numpy().astype(np.float64)
+        x2 = g2[:N].cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(x1)) and np.all(np.isfinite(x2))
+        scale = np.abs(x1).max(axis=0) + 1e-30
+        assert np.all(np.abs(x1 - x2) <= 1e-5 * scale), (name, tile)
+
+
 def test_autograd_function_matches_oracle(R):
     from paper_2602_22625_amd.render import render
     d = synth.make_workload("c0")
