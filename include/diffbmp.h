@@ -107,6 +107,7 @@ int dbmp_time_next_launch(dbmp_ctx *ctx, int stage, void *start_event, void *sto
 /*
  * Stores the bitmap templates in the context: each bitmap is copied with a one-texel zero border
  * (the zero padding of the bilinear sampler) and its bounding box of non-zero texels is found.
+ * DBMP_EINVAL if the padded copy, B x (Hb + 2) x (Wb + 2) texels, would reach 4 GiB.
  * Renders given atlas == NULL use this copy, so a fit loop pays for it once. A render given an
  * atlas replaces it. Asynchronous on `stream`; the caller's atlas may be freed once the work on
  * `stream` has finished.
@@ -260,6 +261,13 @@ long long dbmp_longest_list(dbmp_ctx *ctx, dbmp_stream stream);
  * least one non-zero texel (elsewhere M and its derivatives are exactly zero, Supp. Eqs. S1-S3).
  * Synchronises `stream`; reset != 0 zeroes the count afterwards (synchronously). -1 on error. */
 long long dbmp_support_pairs(dbmp_ctx *ctx, dbmp_stream stream, int reset);
+
+/* Number of times the context's workspace has been reallocated so far (-1 for a NULL context).
+ * The workspace grows (synchronously, outside graph capture) when a call needs more room than any
+ * earlier one: a larger canvas, more primitives or tiles, a larger list capacity or atlas. A growth
+ * releases the old memory, so a HIP graph captured on this context before it refers to freed
+ * addresses and must be captured again; compare the epoch at capture and before a replay. */
+long long dbmp_workspace_epoch(const dbmp_ctx *ctx);
 
 /* Message of the last error on this context ("" if none). Valid until the next call. */
 const char *dbmp_last_error(const dbmp_ctx *ctx);

@@ -67,6 +67,7 @@ def load():
         "dbmp_longest_list": ([P, P], LL),
         "dbmp_support_pairs": ([P, P, I], LL),
         "dbmp_last_error": ([P], ctypes.c_char_p),
+        "dbmp_workspace_epoch": ([P], LL),
         "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
         "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P, I], I),
     }
@@ -232,6 +233,10 @@ def dbmp_support_pairs(ctx, stream, reset=0):
 
 def dbmp_last_error(ctx):
     return load().dbmp_last_error(ctx).decode()
+
+
+def dbmp_workspace_epoch(ctx):
+    return int(load().dbmp_workspace_epoch(ctx))
 
 
 def dbmp_mse_grad(stream, image, target, n, grad, loss):

@@ -1,6 +1,7 @@
 // C ABI of the rasteriser (declared in include/diffbmp.h): context, workspace and launches.
 #include "dbmp_internal.h"
 #include "diffbmp.h"
+#include "workspace.h"
 
 #include <limits.h>
 #include <stdio.h>
@@ -16,15 +17,6 @@ using namespace dbmp;
 static_assert(DBMP_SCHED_GRID == SCHED_GRID && DBMP_SCHED_SORTED == SCHED_SORTED &&
                   DBMP_SCHED_PERSISTENT == SCHED_PERSISTENT,
               "schedule codes of the ABI and the kernels agree");
-
-namespace {
-
-struct Buf {
-    void *p = nullptr;
-    size_t cap = 0;  // bytes
-};
-
-}  // namespace
 
 struct dbmp_ctx {
     int device = 0;
@@ -43,6 +35,7 @@ struct dbmp_ctx {
     bool atlas_valid = false;
     int atlas_B = 0, atlas_Hb = 0, atlas_Wb = 0, atlas_dtype = 0;
     std::vector<ImgDev> imgs_uploaded;  // what the device copy of the descriptors holds
+    long long epoch = 0;                // workspace growths so far (dbmp_workspace_epoch)
     // state of the last forward, for the backward
     bool have_fwd = false;
     bool have_loss = false;
@@ -84,30 +77,50 @@ bool capturing(hipStream_t st)
     return s != hipStreamCaptureStatusNone;
 }
 
-// Grows `b` to at least `bytes` (contents not preserved). Synchronous; refused while the stream
-// is being captured into a graph.
-int ensure(dbmp_ctx *c, Buf &b, size_t bytes, hipStream_t st, const char *what)
+// Device operations of a workspace growth (workspace.h). The device is synchronised before a
+// block is released: a context may have work queued on several streams (a fit's warm-up on a side
+// stream, graph replays), and any of it may still read the old block.
+struct HipOps {
+    dbmp_ctx *c;
+    const char *what;
+    int quiesce()
+    {
+        hipError_t e = hipDeviceSynchronize();
+        return e == hipSuccess ? 0 : hip_fail(c, e, "hipDeviceSynchronize");
+    }
+    void release(void *p) { (void)hipFree(p); }
+    int acquire(void **p, size_t bytes)
+    {
+        if (hipMalloc(p, bytes) == hipSuccess) return 0;
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, DBMP_ENOMEM, std::string("hipMalloc failed for ") + what);
+    }
+    int clear(void *p, size_t bytes)
+    {
+        hipError_t e = hipMemset(p, 0, bytes);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        return e == hipSuccess ? 0 : hip_fail(c, e, "workspace clear");
+    }
+};
+
+// Grows `b` to at least `bytes` (contents not preserved; must_be_zero: the new block is cleared).
+// Synchronous; refused while the stream is being captured into a graph. A growth frees the old
+// block, so graphs captured earlier on this context hold stale addresses: the workspace epoch
+// counts the growths (dbmp_workspace_epoch).
+int ensure(dbmp_ctx *c, Buf &b, size_t bytes, hipStream_t st, const char *what,
+           bool must_be_zero = false)
 {
-    if (bytes == 0) bytes = 16;
-    if (b.cap >= bytes) return DBMP_OK;
+    if (b.cap >= (bytes ? bytes : 16)) return DBMP_OK;
     if (capturing(st))
         return fail(c, DBMP_ESTATE, std::string("workspace '") + what +
                                         "' must grow during graph capture; run the call once "
                                         "before capturing");
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-    const size_t want = bytes + bytes / 4;
-    e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        (void)hipGetLastError();
-        return fail(c, DBMP_ENOMEM, std::string("hipMalloc failed for ") + what);
-    }
-    b.cap = want;
-    return DBMP_OK;
+    HipOps ops{c, what};
+    bool grown = false;
+    const int rc = grow_buffer(b, bytes, must_be_zero, ops, &grown);
+    if (grown) ++c->epoch;
+    return rc;
 }
 
 // List capacities are kept a multiple of 32 entries so every tile's list starts on its own
@@ -132,9 +145,11 @@ int set_atlas_impl(dbmp_ctx *c, hipStream_t st, const void *atlas, int B, int Hb
     if (!atlas || B < 1 || Hb < 2 || Wb < 2) return fail(c, DBMP_EINVAL, "bad atlas shape");
     if (dtype != DBMP_F32 && dtype != DBMP_BF16) return fail(c, DBMP_EINVAL, "bad atlas dtype");
     const int Hp = Hb + 2, Wp = Wb + 2;
-    if ((long long)B * Hp * Wp >= INT_MAX) return fail(c, DBMP_EINVAL, "atlas too large");
-    int rc;
     const size_t esz = dtype == DBMP_F32 ? 4 : 2;
+    if (!atlas_addressable(B, Hb, Wb, (long long)esz))
+        return fail(c, DBMP_EINVAL, "atlas too large (the padded copy must stay below 4 GiB)");
+    c->atlas_valid = false;  // until the new copy is enqueued (a failed growth frees the old one)
+    int rc;
     if ((rc = ensure(c, c->atlas_pad, esz * (size_t)B * Hp * Wp, st, "atlas"))) return rc;
     if ((rc = ensure(c, c->box, 16 * (size_t)B, st, "boxes"))) return rc;
     BinArgs ba{};
@@ -145,20 +160,6 @@ int set_atlas_impl(dbmp_ctx *c, hipStream_t st, const void *atlas, int B, int Hb
     if (e != hipSuccess) return hip_fail(c, e, "atlas launch");
     c->atlas_valid = true;
     c->atlas_B = B; c->atlas_Hb = Hb; c->atlas_Wb = Wb; c->atlas_dtype = dtype;
-    return DBMP_OK;
-}
-
-// Grows a counter buffer that must read as zero; new memory is cleared synchronously.
-int ensure_zeroed(dbmp_ctx *c, Buf &b, size_t bytes, hipStream_t st, const char *what)
-{
-    void *before = b.p;
-    int rc = ensure(c, b, bytes, st, what);
-    if (rc) return rc;
-    if (b.p != before) {
-        hipError_t e = hipMemset(b.p, 0, b.cap);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(c, e, "counter clear");
-    }
     return DBMP_OK;
 }
 
@@ -241,7 +242,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
 
     const size_t ni = imgs.size();
     if ((rc = ensure(c, c->recs, sizeof(PrimRec) * (size_t)n_rows, st, "records"))) return rc;
-    if ((rc = ensure_zeroed(c, c->tile_count, 4 * (size_t)tiles, st, "tile_count"))) return rc;
+    if ((rc = ensure(c, c->tile_count, 4 * (size_t)tiles, st, "tile_count", true))) return rc;
     if ((rc = ensure(c, c->tile_len, 4 * (size_t)tiles, st, "tile_len"))) return rc;
     if ((rc = ensure(c, c->loss_tile, 4 * (size_t)tiles, st, "loss_tile"))) return rc;
     if ((rc = ensure(c, c->lists, 4 * (size_t)tiles * c->list_cap, st, "tile lists"))) return rc;
@@ -257,8 +258,9 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
                         "image descriptors changed during graph capture; run the call once "
                         "before capturing");
         if ((rc = ensure(c, c->imgs, sizeof(ImgDev) * ni, st, "descriptors"))) return rc;
-        hipError_t e = hipStreamSynchronize(st);  // earlier launches may still read the table
-        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        // earlier launches, on any stream, may still read the table
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
         e = hipMemcpy(c->imgs.p, imgs.data(), sizeof(ImgDev) * ni, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(c, e, "descriptor upload");
         c->imgs_uploaded = imgs;
@@ -665,6 +667,8 @@ long long dbmp_support_pairs(dbmp_ctx *c, dbmp_stream stream, int reset)
     if (reset && hipDeviceSynchronize() != hipSuccess) return -1;
     return (long long)v;
 }
+
+long long dbmp_workspace_epoch(const dbmp_ctx *c) { return c ? c->epoch : -1; }
 
 const char *dbmp_last_error(const dbmp_ctx *c) { return c ? c->err.c_str() : "null context"; }
 

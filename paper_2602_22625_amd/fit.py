@@ -45,6 +45,7 @@ class Fitter:
         self.adam_in_binning = fused and accumulate and adam_in_binning
         self.graph = None
         self._graph_steps = 1
+        self._graph_epoch = -1
         self._sized = False
 
     # One Adam iteration, enqueued on the current stream. dbmp_fit_step: binning (with the
@@ -66,6 +67,7 @@ class Fitter:
                            self.target, self.image, self.grad, self.m, self.v, self.step_count,
                            self.lr, self.betas[0], self.betas[1], self.eps)
         self.R._fwd_buffers = (self.image, self.bg)
+        self.R._fwd_shape = (self.N, self.H * self.W)
 
     def flush(self):
         """Apply the Adam update of a gradient left pending by the last step (synchronises)."""
@@ -106,6 +108,12 @@ class Fitter:
         iteration."""
         if not self._sized:
             self._size()
+        if self.graph is not None and \
+                capi.dbmp_workspace_epoch(self.R.ctx) != self._graph_epoch:
+            # the context's workspace was reallocated since the capture (another caller of the
+            # same renderer needed more room): the graph's addresses are stale
+            self.graph = None
+            self.capture(self._graph_steps)
         if self.graph is not None:
             self.graph.replay()
         else:
@@ -151,6 +159,7 @@ class Fitter:
                 self._enqueue()
         self.graph = g
         self._graph_steps = steps_per_graph
+        self._graph_epoch = capi.dbmp_workspace_epoch(self.R.ctx)
 
     def run(self, steps, check_every=50):
         """`steps` Adam iterations; every `check_every` steps the device flags are polled. On a
@@ -266,6 +275,7 @@ class BatchFitter(Fitter):
         self.adam_in_binning = fused and adam_in_binning
         self.graph = None
         self._graph_steps = 1
+        self._graph_epoch = -1
         self._sized = False
 
     def _render(self):
@@ -278,6 +288,7 @@ class BatchFitter(Fitter):
                                    self.grad, self.m, self.v, self.step_count, self.lr,
                                    self.betas[0], self.betas[1], self.eps)
         self.R._fwd_buffers = (self.image, self.bg)
+        self.R._fwd_shape = (self.N, self.image.numel() // 3)
 
     def _cdescs(self):
         return [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))

@@ -31,6 +31,66 @@ def _need(t, name, dtype=None, shape=None):
         raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
 
 
+def _check_rows(t, rows, name):
+    """t must be a [rows, 8] gradient or parameter table."""
+    if t.dim() != 2 or t.shape[1] != 8 or t.shape[0] != rows:
+        raise ValueError("%s must have shape (%d, 8), got %s" % (name, rows, tuple(t.shape)))
+
+
+def _check_numel(t, n, name):
+    if t.numel() != n:
+        raise ValueError("%s must hold %d values (the forward's layout), got %d"
+                         % (name, n, t.numel()))
+
+
+def _batch_layout(descs):
+    """(parameter rows, pixels) a batched call reads and writes."""
+    rows = max(int(d[3]) + int(d[2]) for d in descs)
+    npix = max(int(d[4]) + int(d[0]) * int(d[1]) for d in descs)
+    return rows, npix
+
+
+def check_backward_args(fwd, dL_dimage=None, dL_dalpha=None, out=None, target=None,
+                        n_params=None):
+    """Host-side size checks of a backward against the forward it differentiates. fwd =
+    (rows, npix) of that forward: the kernels read 3 * npix image values (dL/dI or the MSE
+    target), npix alpha values, and add into rows x 8 gradients. Pure shape logic (no device)."""
+    if fwd is None:
+        raise RuntimeError("no forward has run on this renderer")
+    rows, npix = fwd
+    if n_params is not None and int(n_params) != rows:
+        raise ValueError("n_params=%d but the forward read %d parameter rows" % (n_params, rows))
+    if dL_dimage is not None:
+        _check_numel(dL_dimage, 3 * npix, "dL_dimage")
+    if target is not None:
+        _check_numel(target, 3 * npix, "target")
+    if dL_dalpha is not None:
+        _check_numel(dL_dalpha, npix, "dL_dalpha")
+    if out is not None:
+        _check_rows(out, rows, "out")
+
+
+def check_batch_args(descs, params, atlas_idx, image=None, alpha=None, target=None, out=None):
+    """Host-side size checks of a batched call: every image's primitive rows and pixels must lie
+    inside the buffers given. Pure shape logic (no device)."""
+    if not descs:
+        raise ValueError("need at least one image descriptor")
+    rows, npix = _batch_layout(descs)
+    if params.dim() != 2 or params.shape[1] != 8 or params.shape[0] < rows:
+        raise ValueError("params must be [>= %d, 8], got %s" % (rows, tuple(params.shape)))
+    if atlas_idx.numel() < rows:
+        raise ValueError("atlas_idx must hold >= %d values, got %d" % (rows, atlas_idx.numel()))
+    if image is not None:
+        _check_numel(image, 3 * npix, "image")
+    if alpha is not None:
+        _check_numel(alpha, npix, "alpha")
+    if target is not None:
+        _check_numel(target, 3 * npix, "target")
+    if out is not None:
+        _check_rows(out, rows, "out")
+    return rows, npix
+
+
 class Renderer:
     """One dbmp context. `check=True` synchronises after each forward to detect a tile list
     that did not fit, grows the capacity and renders again; `check=False` keeps every call
@@ -46,6 +106,8 @@ class Renderer:
         # image and the background): held until the next forward so they cannot be freed and
         # reused while a backward may still read them
         self._fwd_buffers = ()
+        # (parameter rows, pixels) of the last forward: what a backward may read and write
+        self._fwd_shape = None
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -108,6 +170,7 @@ class Renderer:
         args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, dcode, H, W,
                 bg, bg_pp, alpha_max, tile, image, alpha)
         self._fwd_buffers = (image, alpha, bg)
+        self._fwd_shape = (N, H * W)
         capi.dbmp_render(*args)
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
@@ -135,17 +198,21 @@ class Renderer:
             _need(atlas, "atlas")
             B, Hb, Wb = atlas.shape
             dcode = _dtype_code(atlas)
-        npix = max(int(d[4]) + int(d[0]) * int(d[1]) for d in descs)
+        rows, npix = check_batch_args(descs, params, atlas_idx, image, alpha)
         if image is None:
             image = torch.empty(3 * npix, device=params.device, dtype=torch.float32)
         if alpha is None and with_alpha:
             alpha = torch.empty(npix, device=params.device, dtype=torch.float32)
+        _need(image, "image", torch.float32)
+        if alpha is not None:
+            _need(alpha, "alpha", torch.float32)
         cd = [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))
               for (h, w, n, po, xo) in descs]
         st = capi.stream_handle()
         args = (self.ctx, st, cd, params, atlas_idx, atlas, B, Hb, Wb, dcode, bg,
                 alpha_max, tile, image, alpha)
         self._fwd_buffers = (image, alpha, bg)
+        self._fwd_shape = (rows, npix)
         capi.dbmp_render_batched(*args)
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
@@ -183,14 +250,20 @@ class Renderer:
             bg = torch.ones(3, device=params.device, dtype=torch.float32)
         _need(bg, "bg", torch.float32)
         bg_pp = 0 if bg.numel() == 3 else 1
+        if bg_pp and tuple(bg.shape) != (3, H, W):
+            raise ValueError("bg must have 3 values or shape [3, H, W]")
         if image is None:
             image = torch.empty(3, H, W, device=params.device, dtype=torch.float32)
+        _need(image, "image", torch.float32, (3, H, W))
         if out is None:
             out = torch.zeros(N, 8, device=params.device, dtype=torch.float32)
+        _need(out, "out", torch.float32)
+        _check_rows(out, N, "out")
         st = capi.stream_handle()
         args = (self.ctx, st, params, atlas_idx, N, atlas, B, Hb, Wb, dcode, H, W, bg, bg_pp,
                 alpha_max, tile, target, image, out, 1 if accumulate else 0)
         self._fwd_buffers = (image, bg)
+        self._fwd_shape = (N, H * W)
         capi.dbmp_render_mse(*args)
         if self.check_each:
             rc = capi.dbmp_check(self.ctx, st)
@@ -218,17 +291,30 @@ class Renderer:
             _need(atlas, "atlas")
             B, Hb, Wb = atlas.shape
             dcode = _dtype_code(atlas)
-        npix = max(int(d[4]) + int(d[0]) * int(d[1]) for d in descs)
+        rows, npix = check_batch_args(descs, params, atlas_idx, image, None, target, out)
         if image is None:
             image = torch.empty(3 * npix, device=params.device, dtype=torch.float32)
         if out is None:
-            out = torch.zeros(params.shape[0], 8, device=params.device, dtype=torch.float32)
+            out = torch.zeros(rows, 8, device=params.device, dtype=torch.float32)
+        _need(image, "image", torch.float32)
+        _need(out, "out", torch.float32)
         cd = [capi.ImageDesc(int(h), int(w), int(n), 0, int(po), int(xo))
               for (h, w, n, po, xo) in descs]
+        st = capi.stream_handle()
+        args = (self.ctx, st, cd, params, atlas_idx, atlas, B, Hb, Wb, dcode, bg, alpha_max,
+                tile, target, image, out, 1 if accumulate else 0)
         self._fwd_buffers = (image, bg)
-        capi.dbmp_render_batched_mse(self.ctx, capi.stream_handle(), cd, params, atlas_idx, atlas,
-                                     B, Hb, Wb, dcode, bg, alpha_max, tile, target, image, out,
-                                     1 if accumulate else 0)
+        self._fwd_shape = (rows, npix)
+        capi.dbmp_render_batched_mse(*args)
+        if self.check_each:
+            rc = capi.dbmp_check(self.ctx, st)
+            if rc == capi.DBMP_EOVERFLOW and not accumulate:
+                need = capi.dbmp_longest_list(self.ctx, st)
+                capi.dbmp_reserve(self.ctx, int(need * 1.25) + 16)
+                capi.dbmp_render_batched_mse(*args)
+                rc = capi.dbmp_check(self.ctx, st)
+            if rc != capi.DBMP_OK:
+                raise capi.DbmpError(rc, capi.dbmp_last_error(self.ctx))
         self.generation += 1
         return image, out
 
@@ -237,8 +323,13 @@ class Renderer:
         _need(dL_dimage, "dL_dimage", torch.float32)
         if dL_dalpha is not None:
             _need(dL_dalpha, "dL_dalpha", torch.float32)
+        if n_params is None and out is None:
+            raise ValueError("give n_params or out")
+        check_backward_args(self._fwd_shape, dL_dimage=dL_dimage, dL_dalpha=dL_dalpha, out=out,
+                            n_params=n_params)
         if out is None:
             out = torch.empty(n_params, 8, device=dL_dimage.device, dtype=torch.float32)
+        _need(out, "out", torch.float32)
         capi.dbmp_render_backward(self.ctx, capi.stream_handle(), dL_dimage, dL_dalpha, out)
         return out
 
@@ -248,8 +339,13 @@ class Renderer:
         _need(target, "target", torch.float32)
         if dL_dalpha is not None:
             _need(dL_dalpha, "dL_dalpha", torch.float32)
+        if n_params is None and out is None:
+            raise ValueError("give n_params or out")
+        check_backward_args(self._fwd_shape, target=target, dL_dalpha=dL_dalpha, out=out,
+                            n_params=n_params)
         if out is None:
             out = torch.empty(n_params, 8, device=target.device, dtype=torch.float32)
+        _need(out, "out", torch.float32)
         capi.dbmp_render_backward_mse(self.ctx, capi.stream_handle(), target, dL_dalpha, out,
                                       1 if accumulate else 0)
         return out
