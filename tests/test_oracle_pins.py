@@ -352,21 +352,62 @@ def test_crop_equals_full_and_backward_is_additive_over_pixels():
     assert np.max(np.abs(gin + gout - gfull)) < 1e-12 * max(1.0, np.max(np.abs(gfull)))
 
 
-def test_support_pair_count_bruteforce_small():
-    """Tiny case counted by hand-written loops in Python."""
-    p, idx, atlas = _scene(81, N=5, H=20, W=24, log_s=math.log(4.0))
-    n = oracle.support_pairs_bruteforce(p, 32, 32, 20, 24)
-    cnt = 0
-    for k in range(5):
-        s, c, sn = math.exp(p[k, 2]), math.cos(p[k, 3]), math.sin(p[k, 3])
-        for y in range(20):
-            for x in range(24):
-                dx, dy = x - p[k, 0], y - p[k, 1]
-                U = ((c * dx + sn * dy) / s + 1) / 2 * 31
-                V = ((-sn * dx + c * dy) / s + 1) / 2 * 31
-                if -1 <= math.floor(U) <= 31 and -1 <= math.floor(V) <= 31:
-                    cnt += 1
-    assert n == cnt and n > 0
+def _grid_sample_support(p, Hb, Wb, H, W):
+    """Pixels where torch's bilinear sampler (zero padding, align_corners=True: Eq. 2) gives a
+    non-zero value for a bitmap whose every texel is positive: exactly the pixels whose bilinear
+    footprint reaches a texel inside the bitmap (measure-zero ties aside). The support boundary
+    comes from the library's padding rule, not from a floor bound written here."""
+    bm = torch.full((1, 1, Hb, Wb), 0.5, dtype=torch.float64)
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    n = 0
+    for k in range(p.shape[0]):
+        s = math.exp(p[k, 2])
+        c, sn = math.cos(p[k, 3]), math.sin(p[k, 3])
+        dx, dy = xs - p[k, 0], ys - p[k, 1]
+        grid = torch.stack([(c * dx + sn * dy) / s, (-sn * dx + c * dy) / s], dim=-1)[None]
+        m = F.grid_sample(bm, grid, mode="bilinear", padding_mode="zeros", align_corners=True)
+        n += int((m > 0).sum())
+    return n
+
+
+@pytest.mark.parametrize("seed,Hb,Wb", [(81, 32, 32), (82, 17, 40), (83, 64, 64)])
+def test_support_pair_count_equals_grid_sample_support(seed, Hb, Wb):
+    """The brute-force count of evaluated (pixel, primitive) pairs equals the number of pixels
+    where FP64 grid_sample of a strictly positive bitmap is non-zero (an off-by-one in the
+    support bound, a transposed H/W or a wrong scale in the count would break it). Primitives
+    straddle the canvas edges and some lie fully outside."""
+    g = np.random.default_rng(seed)
+    H, W, N = 23, 29, 9
+    p = np.zeros((N, 8))
+    p[:, 0] = g.uniform(-8, W + 8, N)
+    p[:, 1] = g.uniform(-8, H + 8, N)
+    p[:, 2] = g.normal(math.log(5.0), 0.4, N)
+    p[:, 3] = g.uniform(0, 2 * math.pi, N)
+    p[N - 1, :2] = (-40.0, 10.0)  # off canvas: contributes no pair
+    n = oracle.support_pairs_bruteforce(p, Hb, Wb, H, W)
+    assert n == _grid_sample_support(p, Hb, Wb, H, W)
+    assert n > 50
+    # and on a crop: the count of a window is the window's share
+    crop = (4, 3, 17, 11)
+    x0, y0, w, h = crop
+    q = p.copy()
+    q[:, 0] -= x0
+    q[:, 1] -= y0
+    assert oracle.support_pairs_bruteforce(p, Hb, Wb, H, W, crop=crop) == \
+        _grid_sample_support(q, Hb, Wb, h, w)
+
+
+def test_psnr_closed_form():
+    """PSNR = 10 log10(1 / MSE) with peak 1 (the paper's evaluation metric): a constant error of
+    0.1 on every value gives 20 dB; 0.01 gives 40 dB; an error on one of n values scales by n."""
+    g = np.random.default_rng(2)
+    t = g.uniform(0.2, 0.8, (3, 8, 5))
+    assert abs(oracle.psnr(t + 0.1, t) - 20.0) < 1e-9
+    assert abs(oracle.psnr(t - 0.01, t) - 40.0) < 1e-9
+    e = t.copy()
+    e[1, 2, 3] += 0.5
+    assert abs(oracle.psnr(e, t) - 10.0 * math.log10(t.size / 0.25)) < 1e-9
 
 
 # ------------------------------------------------------------------------------------------
