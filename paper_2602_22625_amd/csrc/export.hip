@@ -1,0 +1,210 @@
+// Layer export (Sec. 3.1.3; Supp. "PSD export"), declared in include/dbmp_export.h.
+//
+// Stage 1: one lane per primitive finds the box of export pixels its bilinear support can reach
+// (float64, as the binning), then one workgroup turns the box areas into offsets (an exclusive
+// int64 scan). Stage 2: a grid of (primitive, tile row, tile column) workgroups of 16 x 16 export
+// pixels; each lane evaluates its pixel's alpha (the forward's arithmetic: float64 coordinates,
+// float32 bilinear sample) and writes it into the primitive's own packed box. Every output value
+// has exactly one writer, so no atomics.
+#include "dbmp_export.h"
+#include "dbmp_internal.h"
+#include "diffbmp.h"
+
+#include <limits.h>
+#include <math.h>
+
+namespace dbmp {
+namespace {
+
+constexpr int EXP_T = 16;
+
+// Canvas point of export pixel X: (X + 0.5) / rho - 0.5; export coordinate of canvas point x:
+// rho (x + 0.5) - 0.5.
+__global__ void __launch_bounds__(256)
+k_export_boxes(const float *__restrict__ params, int N, int Hb, int Wb, int HH, int WW,
+               double rho, int *__restrict__ boxes, long long *__restrict__ area,
+               int *__restrict__ max_wh)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const float *p = params + (size_t)i * 8;
+    bool fin = true;
+    for (int q = 0; q < 8; ++q) fin = fin && isfinite(p[q]);
+    int x0 = 0, y0 = 0, w = 0, h = 0;
+    const double s = exp((double)p[2]);
+    if (fin && s > 0.0 && isfinite(s)) {
+        double st, ct;
+        sincos((double)p[3], &st, &ct);
+        const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1);
+        double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+        for (int c = 0; c < 4; ++c) {  // corners of -1 <= U <= Wb, -1 <= V <= Hb
+            const double U = (c & 1) ? (double)Wb : -1.0, V = (c & 2) ? (double)Hb : -1.0;
+            const double u = U / cu - 1.0, v = V / cv - 1.0;
+            const double X = rho * ((double)p[0] + s * (ct * u - st * v) + 0.5) - 0.5;
+            const double Y = rho * ((double)p[1] + s * (st * u + ct * v) + 0.5) - 0.5;
+            xmin = fmin(xmin, X); xmax = fmax(xmax, X);
+            ymin = fmin(ymin, Y); ymax = fmax(ymax, Y);
+        }
+        const double mg = 1e-3;  // conservative against rounding
+        const double fx0 = fmax(ceil(xmin - mg), 0.0), fx1 = fmin(floor(xmax + mg), WW - 1.0);
+        const double fy0 = fmax(ceil(ymin - mg), 0.0), fy1 = fmin(floor(ymax + mg), HH - 1.0);
+        if (fx0 <= fx1 && fy0 <= fy1) {
+            x0 = (int)fx0; y0 = (int)fy0;
+            w = (int)(fx1 - fx0) + 1; h = (int)(fy1 - fy0) + 1;
+        }
+    }
+    boxes[4 * i + 0] = x0; boxes[4 * i + 1] = y0; boxes[4 * i + 2] = w; boxes[4 * i + 3] = h;
+    area[i] = (long long)w * h;
+    if (w) { atomicMax(max_wh, w); atomicMax(max_wh + 1, h); }
+}
+
+__global__ void k_export_init(int *max_wh)
+{
+    max_wh[0] = 0;
+    max_wh[1] = 0;
+}
+
+// Exclusive scan of the N areas into offsets[0 .. N] by one workgroup of 1024 lanes.
+__global__ void __launch_bounds__(1024) k_export_offsets(long long *__restrict__ off, int N)
+{
+    __shared__ long long wsum[16];
+    __shared__ long long carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int b0 = 0; b0 < N; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const long long x = i < N ? off[i] : 0;
+        long long incl = x;
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        long long pre = carry;
+        for (int q = 0; q < wave; ++q) pre += wsum[q];
+        __syncthreads();
+        if (i < N) off[i] = pre + incl - x;
+        if (threadIdx.x == 1023) carry = pre + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[N] = carry;
+}
+
+template <typename TexT>
+__device__ __forceinline__ float tex_at(const TexT *__restrict__ bm, int Hb, int Wb, int r, int c)
+{
+    return (r >= 0 && r < Hb && c >= 0 && c < Wb) ? texel<TexT>(bm[(size_t)r * Wb + c]) : 0.f;
+}
+
+template <typename TexT>
+__global__ void __launch_bounds__(EXP_T * EXP_T)
+k_export_layers(const float *__restrict__ params, const int *__restrict__ idx, int B,
+                const TexT *__restrict__ atlas, int Hb, int Wb, double rho, float alpha_max,
+                const int *__restrict__ boxes, const long long *__restrict__ offsets,
+                float *__restrict__ alpha_out, float *__restrict__ colour_out)
+{
+    const int i = blockIdx.x;
+    const int bw = boxes[4 * i + 2], bh = boxes[4 * i + 3];
+    const float *p = params + (size_t)i * 8;
+    if (blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 3)
+        colour_out[3 * i + threadIdx.x] = (float)(1.0 / (1.0 + exp(-(double)p[5 + threadIdx.x])));
+    const int lx = threadIdx.x % EXP_T, ly = threadIdx.x / EXP_T;
+    const int bx = blockIdx.z * EXP_T + lx, by = blockIdx.y * EXP_T + ly;
+    if (bx >= bw || by >= bh) return;
+    const int k = idx[i];
+    float a = 0.f;
+    if (k >= 0 && k < B) {
+        // the forward's map (float64): U = cu (u + 1), u = (cos dx + sin dy) / s
+        const double s = exp((double)p[2]);
+        double st, ct;
+        sincos((double)p[3], &st, &ct);
+        const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1);
+        const double X = boxes[4 * i] + bx, Y = boxes[4 * i + 1] + by;
+        const double dx = (X + 0.5) / rho - 0.5 - (double)p[0];
+        const double dy = (Y + 0.5) / rho - 0.5 - (double)p[1];
+        const double U = cu * ((ct * dx + st * dy) / s + 1.0);
+        const double V = cv * ((-st * dx + ct * dy) / s + 1.0);
+        const double u0 = floor(U), v0 = floor(V);
+        if (u0 >= -1.0 && u0 <= Wb - 1.0 && v0 >= -1.0 && v0 <= Hb - 1.0) {
+            const int iu = (int)u0, iv = (int)v0;
+            const float wu = (float)(U - u0), wv = (float)(V - v0);
+            const TexT *bm = atlas + (size_t)k * Hb * Wb;
+            const float p00 = tex_at(bm, Hb, Wb, iv, iu), p01 = tex_at(bm, Hb, Wb, iv, iu + 1);
+            const float p10 = tex_at(bm, Hb, Wb, iv + 1, iu), p11 = tex_at(bm, Hb, Wb, iv + 1, iu + 1);
+            const float top = fmaf(wu, p01 - p00, p00), bot = fmaf(wu, p11 - p10, p10);
+            const float M = fmaf(wv, bot - top, top);
+            a = (float)((double)alpha_max / (1.0 + exp(-(double)p[4]))) * M;
+        }
+    }
+    alpha_out[offsets[i] + (long long)by * bw + bx] = a;
+}
+
+int launched() { return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP; }
+
+bool export_canvas(int H, int W, double rho, int *HH, int *WW)
+{
+    if (H < 1 || W < 1 || !(rho > 0.0 && rho <= 64.0)) return false;
+    const double hh = nearbyint(H * rho), ww = nearbyint(W * rho);
+    if (hh < 1 || ww < 1 || hh * ww >= (double)INT_MAX) return false;
+    *HH = (int)hh;
+    *WW = (int)ww;
+    return true;
+}
+
+}  // namespace
+}  // namespace dbmp
+
+using namespace dbmp;
+
+extern "C" {
+
+int dbmp_export_boxes(dbmp_export_stream stream, const float *params, int N, int Hb, int Wb,
+                      int H, int W, double rho, int32_t *boxes, long long *offsets,
+                      int32_t *max_wh)
+{
+    int HH = 0, WW = 0;
+    if (N < 0 || Hb < 2 || Wb < 2 || !export_canvas(H, W, rho, &HH, &WW)) return DBMP_EINVAL;
+    if (!offsets || !max_wh || (N > 0 && (!params || !boxes))) return DBMP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    k_export_init<<<1, 1, 0, st>>>(max_wh);
+    if (N > 0)
+        k_export_boxes<<<(N + 255) / 256, 256, 0, st>>>(params, N, Hb, Wb, HH, WW, rho, boxes,
+                                                       offsets, max_wh);
+    k_export_offsets<<<1, 1024, 0, st>>>(offsets, N);
+    return launched();
+}
+
+int dbmp_export_layers(dbmp_export_stream stream, const float *params, const int32_t *atlas_idx,
+                       int N, const void *atlas, int B, int Hb, int Wb, int atlas_dtype, int H,
+                       int W, double rho, float alpha_max, const int32_t *boxes,
+                       const long long *offsets, int max_w, int max_h, float *alpha_out,
+                       float *colour_out)
+{
+    int HH = 0, WW = 0;
+    if (N < 0 || B < 1 || Hb < 2 || Wb < 2 || !export_canvas(H, W, rho, &HH, &WW))
+        return DBMP_EINVAL;
+    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16) return DBMP_EINVAL;
+    if (!(alpha_max > 0.f && alpha_max <= 1.f)) return DBMP_EINVAL;
+    if (max_w < 0 || max_h < 0 || max_w > WW || max_h > HH) return DBMP_EINVAL;
+    if (N == 0) return DBMP_OK;
+    if (!params || !atlas_idx || !atlas || !boxes || !offsets || !colour_out) return DBMP_EINVAL;
+    if (max_w > 0 && !alpha_out) return DBMP_EINVAL;
+    const int ty = max_h > 0 ? (max_h + EXP_T - 1) / EXP_T : 1;
+    const int tx = max_w > 0 ? (max_w + EXP_T - 1) / EXP_T : 1;
+    if (ty > 65535 || tx > 65535) return DBMP_EINVAL;
+    const dim3 grid(N, ty, tx);
+    hipStream_t st = (hipStream_t)stream;
+    if (atlas_dtype == DBMP_F32)
+        k_export_layers<float><<<grid, EXP_T * EXP_T, 0, st>>>(
+            params, atlas_idx, B, (const float *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
+            alpha_out, colour_out);
+    else
+        k_export_layers<uint16_t><<<grid, EXP_T * EXP_T, 0, st>>>(
+            params, atlas_idx, B, (const uint16_t *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
+            alpha_out, colour_out);
+    return launched();
+}
+
+}  // extern "C"
