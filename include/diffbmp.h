@@ -180,6 +180,37 @@ int dbmp_render_mse(dbmp_ctx *ctx, dbmp_stream stream, const float *params,
                     float alpha_max, int tile, const float *target, float *image,
                     float *dL_dparams, int accumulate);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): dbmp_render_mse with no context. The workspace a
+ * context would own lives in one static device array of DBMP_NOALLOC_SCRATCH_MB MiB per device,
+ * held from the library's first use on that device until the process ends; the call allocates
+ * and frees nothing. Results are those of dbmp_render_mse with the default schedule (the image
+ * bit for bit, the gradient up to the order of its float atomics).
+ *   arguments as dbmp_render_mse, on the current HIP device, with the atlas given every call;
+ *   list_capacity  entries per tile list (>= 1; rounded up to a multiple of 32): the most
+ *                  primitives that may overlap one screen tile;
+ *   status         out, device int32 [4], cleared by the call, then {a tile list overflowed
+ *                  (that tile is neither rendered nor differentiated), an atlas index out of
+ *                  range, a non-finite parameter or texel, 0}: non-zero raises it;
+ *   scratch_bytes  out, host, may be NULL: the scratch these sizes need (written also when the
+ *                  call is refused).
+ * DBMP_ENOMEM (nothing enqueued) if the sizes need more than the static array: about
+ * 192 N + 4 n_tiles list_capacity + 8 H W + the padded atlas + 12 n_tiles bytes, so 2048 x 2048
+ * with 65,536 primitives fits with list_capacity 96. DBMP_EINVAL for bad arguments (as
+ * dbmp_render_mse), DBMP_EHIP if a launch failed. The first call on a device resolves the
+ * array's address (hipGetSymbolAddress): make it outside graph capture. Every call on a device
+ * uses that device's array, so calls that overlap in time on one device (other streams, other
+ * host threads) race and must not be issued; consecutive calls on one stream are safe.
+ */
+#define DBMP_NOALLOC_SCRATCH_MB 64
+int dbmp_render_mse_noalloc(dbmp_stream stream, const float *params, const int32_t *atlas_idx,
+                            int N, const void *atlas, int B, int Hb, int Wb, int atlas_dtype,
+                            int H, int W, const float *bg, int bg_per_pixel, float alpha_max,
+                            int tile, int list_capacity, const float *target, float *image,
+                            float *dL_dparams, int accumulate, int32_t *status,
+                            size_t *scratch_bytes);
+
 /* Sum over pixels and channels of (I - target)^2 of each image of the last
  * dbmp_render_backward_mse, written to out[0 .. n_images) (device float32). Asynchronous. */
 int dbmp_mse_loss(dbmp_ctx *ctx, dbmp_stream stream, float *out);

@@ -16,6 +16,7 @@ DBMP_OK, DBMP_EINVAL, DBMP_ENOMEM, DBMP_EHIP, DBMP_EOVERFLOW, DBMP_ESTATE, DBMP_
     0, -1, -2, -3, -4, -5, -6
 DBMP_F32, DBMP_BF16 = 0, 1
 DBMP_SCHED_GRID, DBMP_SCHED_SORTED, DBMP_SCHED_PERSISTENT = 0, 1, 2
+DBMP_NOALLOC_SCRATCH_MB = 64  # include/diffbmp.h
 STATUS_NAMES = {0: "DBMP_OK", -1: "DBMP_EINVAL", -2: "DBMP_ENOMEM", -3: "DBMP_EHIP",
                 -4: "DBMP_EOVERFLOW", -5: "DBMP_ESTATE", -6: "DBMP_ENONFINITE"}
 
@@ -68,6 +69,8 @@ def load():
         "dbmp_support_pairs": ([P, P, I], LL),
         "dbmp_last_error": ([P], ctypes.c_char_p),
         "dbmp_workspace_epoch": ([P], LL),
+        "dbmp_render_mse_noalloc": ([P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, I, P, P, P, I,
+                                     P, ctypes.POINTER(ctypes.c_size_t)], I),
         "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
         "dbmp_adam_step": ([P, P, P, P, P, LL, F, F, F, F, P, I], I),
     }
@@ -161,6 +164,24 @@ def dbmp_render_mse(ctx, stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_d
                                             int(bg_per_pixel), float(alpha_max), int(tile),
                                             ptr(target), ptr(image), ptr(dL_dparams),
                                             int(accumulate)))
+
+
+def dbmp_render_mse_noalloc(stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dtype, H, W,
+                            bg, bg_per_pixel, alpha_max, tile, list_capacity, target, image,
+                            dL_dparams, accumulate, status):
+    """Returns the scratch bytes the call used; raises DbmpError (with the bytes the sizes need
+    when the static scratch is too small)."""
+    need = ctypes.c_size_t(0)
+    rc = load().dbmp_render_mse_noalloc(stream, ptr(params), ptr(atlas_idx), int(N), ptr(atlas),
+                                        int(B), int(Hb), int(Wb), int(atlas_dtype), int(H),
+                                        int(W), ptr(bg), int(bg_per_pixel), float(alpha_max),
+                                        int(tile), int(list_capacity), ptr(target), ptr(image),
+                                        ptr(dL_dparams), int(accumulate), ptr(status),
+                                        ctypes.byref(need))
+    if rc != DBMP_OK:
+        raise DbmpError(rc, "dbmp_render_mse_noalloc: these sizes need %d scratch bytes"
+                        % need.value)
+    return need.value
 
 
 def dbmp_render_batched_mse(ctx, stream, descs, params, atlas_idx, atlas, B, Hb, Wb,

@@ -90,3 +90,29 @@ def test_host_argument_checks_need_no_device():
                                        1.0, 16, None, None, None, 0) == capi.DBMP_EINVAL
     h = ctypes.c_void_p()
     assert lib.dbmp_create(ctypes.byref(h), 0, -5) == capi.DBMP_EINVAL
+
+
+def test_noalloc_host_checks_need_no_device():
+    """dbmp_render_mse_noalloc checks its arguments and its scratch need before any HIP call:
+    bad arguments give DBMP_EINVAL, sizes beyond the static scratch DBMP_ENOMEM with the bytes
+    they need reported (dummy non-null pointers are never dereferenced on the host)."""
+    lib = capi.load()
+    need = ctypes.c_size_t(0)
+    fake = ctypes.c_void_p(16)
+    args = [None, fake, fake, 64, fake, 1, 32, 32, 0, 128, 128, fake, 0, 1.0, 16, 64, fake,
+            fake, fake, 0, fake, ctypes.byref(need)]
+    bad = list(args)
+    bad[16] = None  # no target
+    assert lib.dbmp_render_mse_noalloc(*bad) == capi.DBMP_EINVAL
+    bad = list(args)
+    bad[14] = 12    # tile size
+    assert lib.dbmp_render_mse_noalloc(*bad) == capi.DBMP_EINVAL
+    bad = list(args)
+    bad[15] = 0     # list capacity
+    assert lib.dbmp_render_mse_noalloc(*bad) == capi.DBMP_EINVAL
+    big = list(args)
+    big[9] = big[10] = 4096  # 4096 x 4096: 128 MiB of per-pixel state alone
+    assert lib.dbmp_render_mse_noalloc(*big) == capi.DBMP_ENOMEM
+    assert need.value > capi.DBMP_NOALLOC_SCRATCH_MB << 20
+    assert need.value >= 8 * 4096 * 4096
+
