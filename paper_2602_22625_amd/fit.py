@@ -46,6 +46,7 @@ class Fitter:
         self.graph = None
         self._graph_steps = 1
         self._graph_epoch = -1
+        self._hold = None
         self._sized = False
 
     # One Adam iteration, enqueued on the current stream. dbmp_fit_step: binning (with the
@@ -77,6 +78,11 @@ class Fitter:
                                 self.eps, self.step_count, zero_grad=1)
             self.step_count[2] = 0
         return self
+
+    def _held_step(self):
+        if self._hold is not None:
+            self.params.copy_(self._hold)
+        self._enqueue()
 
     def _enqueue(self):
         st = capi.stream_handle()
@@ -113,7 +119,7 @@ class Fitter:
             # the context's workspace was reallocated since the capture (another caller of the
             # same renderer needed more room): the graph's addresses are stale
             self.graph = None
-            self.capture(self._graph_steps)
+            self.capture(self._graph_steps, self._hold)
         if self.graph is not None:
             self.graph.replay()
         else:
@@ -134,21 +140,25 @@ class Fitter:
         for t, c in zip(self._state(), snap):
             t.copy_(c)
 
-    def capture(self, steps_per_graph=1):
+    def capture(self, steps_per_graph=1, hold=None):
         """Capture `steps_per_graph` Adam iterations into one HIP graph (replayed by step()):
         several iterations per replay spread the host's replay cost, the optimiser state being
         on the device. A warm-up step runs first on a side stream (first launches of every
         kernel, no workspace growth inside the capture); its effect on the optimiser state is
-        undone, so capturing does not alter the trajectory."""
+        undone, so capturing does not alter the trajectory.
+        hold: a device tensor of parameters; every captured iteration first copies it into the
+        fit's parameters (one device copy), so that each step starts from the same primitives:
+        a measurement of the step at a fixed state, which the number of steps cannot move."""
         if steps_per_graph < 1:
             raise ValueError("steps_per_graph must be >= 1")
         if not self._sized:
             self._size()
+        self._hold = hold
         snap = self.snapshot()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self._enqueue()
+            self._held_step()
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         self.restore(snap)
@@ -156,7 +166,7 @@ class Fitter:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             for _ in range(steps_per_graph):
-                self._enqueue()
+                self._held_step()
         self.graph = g
         self._graph_steps = steps_per_graph
         self._graph_epoch = capi.dbmp_workspace_epoch(self.R.ctx)
@@ -180,7 +190,7 @@ class Fitter:
                 capi.dbmp_reserve(self.R.ctx, int(need * max(self.headroom, 1.25)) + 1)
                 if self.graph is not None:
                     self.graph = None
-                    self.capture(gs)
+                    self.capture(gs, self._hold)
                 continue
             if rc != capi.DBMP_OK:
                 raise capi.DbmpError(rc, capi.dbmp_last_error(self.R.ctx))
@@ -276,6 +286,7 @@ class BatchFitter(Fitter):
         self.graph = None
         self._graph_steps = 1
         self._graph_epoch = -1
+        self._hold = None
         self._sized = False
 
     def _render(self):
