@@ -406,7 +406,7 @@ def bench_c4(args, torch):
     net = ci.InitNet(seed=0)
     t0 = time.perf_counter()
     final = ci.train(net, tg4, fit4, epochs=args.c4_epochs, batch=64, lr=2e-3,
-                     image_weight=4.0, param_weight=0.1)
+                     image_weight=16.0, param_weight=0.1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log("c4: %d epochs in %.1f s, loss %.4f" % (args.c4_epochs, t_train, final))
@@ -430,7 +430,7 @@ def bench_c4(args, torch):
         "training_pairs": args.c4_pairs, "data_generation_s": round(t_data, 2),
         "training_epochs": args.c4_epochs, "training_s": round(t_train, 2),
         "training_final_loss": round(final, 5), "weights": int(net.n_params),
-        "training_loss": "0.1 x parameter regression + 4 x image MSE through the renderer",
+        "training_loss": "0.1 x parameter regression + 16 x image MSE through the renderer",
     }
     log("c4: learned %.2f ms vs plain %.2f ms (median), %d/%d wins, %d fallbacks"
         % (res["median_t_learned_ms"], res["median_t_plain_ms"], res["wins"], res["n"],

@@ -82,15 +82,17 @@ int dbmp_cnn_param_loss(void *stream, const float *pred, const float *target,
                         const float *extra_scale8, uint16_t *dpred, float *loss);
 
 /* Per-column affine coding of n_rows parameter rows [n_rows][8], row r being slot r % slots of
- * a grid x grid template with cells of `cell` pixels: with centre(r, q) the slot's cell centre
- * for q = 0 (x) and q = 1 (y) and 0 otherwise, and clip() limiting every column but the angle
- * (3) to [-clip, clip],
+ * a grid x grid template with cells of `cell` pixels. Slots are numbered one block of
+ * block x block cells at a time: slot k is cell (k % block^2) (row-major) of block
+ * k / block^2, the blocks taken row-major over the grid (block = 1: the cells row-major;
+ * block must divide grid). With centre(r, q) the slot's cell centre for q = 0 (x) and q = 1 (y)
+ * and 0 otherwise, and clip() limiting every column but the angle (3) to [-clip, clip],
  *     decode != 0:  out = clip(in) * scale8[q] + bias8[q] + centre(r, q)
  *     decode == 0:  out = clip((in - bias8[q] - centre(r, q)) / scale8[q]).
  * scale8 and bias8 are HOST arrays (scale8[q] != 0). in and out may not overlap. */
 int dbmp_cnn_code_params(void *stream, const float *in, long long n_rows, int slots, int grid,
-                         float cell, const float *scale8, const float *bias8, float clip,
-                         int decode, float *out);
+                         int block, float cell, const float *scale8, const float *bias8,
+                         float clip, int decode, float *out);
 
 #ifdef __cplusplus
 }

@@ -99,15 +99,24 @@ def param_loss(pred, target, weights8, scale):
     return float(L.sum() * scale), (G * scale).reshape(np.shape(pred))
 
 
-def code_params(x, slots, grid, cell, scale8, bias8, clip, decode):
+def code_params(x, slots, grid, block, cell, scale8, bias8, clip, decode):
     """Per-column affine coding of parameter rows (the initialiser's output coding): row r is
     slot r % slots of a grid x grid template whose cell centre offsets x (column 0) and y
-    (column 1); every column but the angle (3) is clipped to [-clip, clip] in code space."""
+    (column 1); every column but the angle (3) is clipped to [-clip, clip] in code space.
+    Slots are numbered block x block cells at a time: slot k sits at position k % block^2
+    (row-major) of block k // block^2, the blocks taken row-major over the grid."""
     x = np.asarray(x, np.float64).reshape(-1, 8)
     r = np.arange(x.shape[0]) % slots
     centre = np.zeros_like(x)
-    centre[:, 0] = (r % grid + 0.5) * cell
-    centre[:, 1] = (r // grid + 0.5) * cell
+    col = np.zeros(x.shape[0], np.int64)
+    row = np.zeros(x.shape[0], np.int64)
+    for k in range(x.shape[0]):  # one slot at a time, as the definition reads
+        blk, pos = divmod(int(r[k]), block * block)
+        brow, bcol = divmod(blk, grid // block)
+        row[k] = brow * block + pos // block
+        col[k] = bcol * block + pos % block
+    centre[:, 0] = (col + 0.5) * cell
+    centre[:, 1] = (row + 0.5) * cell
     s = np.asarray(scale8, np.float64)
     b = np.asarray(bias8, np.float64)
     keep = np.arange(8) != 3

@@ -84,7 +84,7 @@ def load():
         "dbmp_cnn_cast_weights": ([P, P, I, I, I, P, P], I),
         "dbmp_cnn_pack_input": ([P, P, I, I, I, P], I),
         "dbmp_cnn_param_loss": ([P, P, P, P, LL, F, P, P, P, P], I),
-        "dbmp_cnn_code_params": ([P, P, LL, I, I, F, P, P, F, I, P], I),
+        "dbmp_cnn_code_params": ([P, P, LL, I, I, I, F, P, P, F, I, P], I),
     })
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -345,10 +345,10 @@ def dbmp_cnn_param_loss(stream, pred, target, weights8, n, scale, dpred, loss, e
                 "dbmp_cnn_param_loss")
 
 
-def dbmp_cnn_code_params(stream, src, n_rows, slots, grid, cell, scale8, bias8, clip, decode,
-                         out):
+def dbmp_cnn_code_params(stream, src, n_rows, slots, grid, block, cell, scale8, bias8, clip,
+                         decode, out):
     sc, bi = _host8(scale8), _host8(bias8)
     return _cnn(load().dbmp_cnn_code_params(stream, ptr(src), int(n_rows), int(slots), int(grid),
-                                            float(cell), sc[0], bi[0], float(clip), int(decode),
-                                            ptr(out)),
+                                            int(block), float(cell), sc[0], bi[0], float(clip),
+                                            int(decode), ptr(out)),
                 "dbmp_cnn_code_params")

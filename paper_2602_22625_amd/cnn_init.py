@@ -3,16 +3,22 @@ trained on (target, parameters after 500 plain Adam steps) pairs that the plain 
 generates, run on the library's bf16 MFMA layer kernels (include/dbmp_cnn.h).
 
 Network: six 3x3 stride-2 convolutions with ReLU (3 -> 32 -> 64 -> 128 -> 256 -> 256 -> 256
-channels, 256^2 -> 4^2 pixels), then a dense layer 4096 -> 64 with ReLU and a dense layer
-64 -> 1024 x 8 (about 2.4 M weights). float32 master weights, bf16 copies for the kernels,
-float32 accumulation; Adam on the master weights with the library's Adam kernel.
+channels, 256^2 -> 4^2 pixels), then a two-layer MLP head applied at each of the 16 positions of
+the last 4 x 4 x 256 feature map with shared weights: 256 -> 512 with ReLU, then 512 -> 512, the
+8 parameters of the 64 slots of that position's 8 x 8 block of cells (about 1.96 M weights). A
+head over the flattened map (4096 -> 64 -> 8192) was tried first: its 64-unit bottleneck had to
+carry the colours of all 1,024 slots at once and capped the start at about 15 dB, where the
+position-wise head, whose receptive field (127 px) covers its 64 x 64 px block, starts near 20 dB.
+float32 master weights, bf16 copies for the kernels, float32 accumulation; Adam on the master
+weights with the library's Adam kernel.
 
 Supervision (slot template): every fit starts from the same template, in which slot i (row i of
-the 1024 primitives) keeps one atlas index for all targets and starts at a uniform point of cell
-i of a 32 x 32 grid. Row i of the fitted parameters then means the same primitive across
-targets, and the network regresses them: positions as offsets from the cell centre in cell
-units, log-scale standardised, logits halved, the angle through 1 - cos(difference) (a full
-turn costs nothing). The plain random initialisation from the same template remains the
+the 1,024 primitives) keeps one atlas index for all targets and starts at a uniform point of its
+cell of a 32 x 32 grid (synth.slot_cells: slots numbered 8 x 8 cells at a time, so the 64 rows a
+head position writes are consecutive). Row i of the fitted parameters then means the same
+primitive across targets, and the network regresses them: positions as offsets from the cell
+centre in cell units, log-scale standardised, logits halved, the angle through 1 - cos(difference)
+(a full turn costs nothing). The plain random initialisation from the same template remains the
 fallback: the learned start is used only if its image error is below the random start's.
 """
 from __future__ import annotations
@@ -31,9 +37,13 @@ IMG = 256
 SLOTS = synth.SLOT_GRID * synth.SLOT_GRID
 LOG_S_MEAN, LOG_S_STD = math.log(12.0), 0.5
 CONV = [(8, 32), (32, 64), (64, 128), (128, 256), (256, 256), (256, 256)]
-FLAT = 4 * 4 * 256
-HIDDEN = 64
+POS = 4 * 4                                 # positions of the last feature map
+FEAT = 256                                  # its channels: the head's input per position
+HIDDEN = 512
+BLOCK = synth.SLOT_BLOCK                    # a position's slots: BLOCK x BLOCK cells
+POS_OUT = BLOCK * BLOCK * 8                 # the head's output per position
 OUT = SLOTS * 8
+assert POS * BLOCK * BLOCK == SLOTS
 # loss weight per parameter column: x, y, log_s, theta, nu, c_r, c_g, c_b (angles of star and
 # stroke bitmaps are ambiguous up to their symmetry: low weight)
 LOSS_W = (1.0, 1.0, 1.0, 0.1, 1.0, 1.0, 1.0, 1.0)
@@ -54,8 +64,8 @@ def _code(x, decode):
     x = x.contiguous()
     out = torch.empty_like(x)
     n_rows = x.numel() // 8
-    capi.dbmp_cnn_code_params(capi.stream_handle(), x, n_rows, SLOTS, synth.SLOT_GRID, CELL,
-                              CODE_SCALE, CODE_BIAS, CLIP, 1 if decode else 0, out)
+    capi.dbmp_cnn_code_params(capi.stream_handle(), x, n_rows, SLOTS, synth.SLOT_GRID, BLOCK,
+                              CELL, CODE_SCALE, CODE_BIAS, CLIP, 1 if decode else 0, out)
     return out
 
 
@@ -79,7 +89,7 @@ class InitNet:
         self.hidden = hidden
         # (kind, R, T, C): weight [R][T][C] (+ bias [R]); conv: R = Cout, T = 9, C = Cin
         self.layers = [("conv", co, 9, ci) for ci, co in CONV]
-        self.layers += [("fc", hidden, 1, FLAT), ("fc", OUT, 1, hidden)]
+        self.layers += [("fc", hidden, 1, FEAT), ("fc", POS_OUT, 1, hidden)]
         sizes = []
         for _, R, T, C in self.layers:
             sizes += [R * T * C, R]
@@ -131,8 +141,8 @@ class InitNet:
             s //= 2
             self.acts.append(torch.empty(B, s, s, co, device=dev, dtype=bf))
             self.dacts.append(torch.empty(B, s, s, co, device=dev, dtype=bf))
-        self.h = torch.empty(B, self.hidden, device=dev, dtype=bf)
-        self.dh = torch.empty(B, self.hidden, device=dev, dtype=bf)
+        self.h = torch.empty(B * POS, self.hidden, device=dev, dtype=bf)
+        self.dh = torch.empty(B * POS, self.hidden, device=dev, dtype=bf)
         self.out = torch.empty(B, OUT, device=dev)
         self.dout = torch.empty(B, OUT, device=dev, dtype=bf)
         self._B = B
@@ -149,10 +159,12 @@ class InitNet:
                                        self.acts[l], None)
             x, s = self.acts[l], s // 2
         L = len(CONV)
-        capi.dbmp_cnn_linear_forward(st, x, B, FLAT, self.wb[L], self.b[L], self.hidden, 1,
+        # the head: NHWC makes the last map B*16 rows of 256 features, and its output rows of
+        # 512 values are the slots of one block each, i.e. [B][SLOTS][8] in slot order
+        capi.dbmp_cnn_linear_forward(st, x, B * POS, FEAT, self.wb[L], self.b[L], self.hidden, 1,
                                      self.h, None)
-        capi.dbmp_cnn_linear_forward(st, self.h, B, self.hidden, self.wb[L + 1], self.b[L + 1],
-                                     OUT, 0, None, self.out)
+        capi.dbmp_cnn_linear_forward(st, self.h, B * POS, self.hidden, self.wb[L + 1],
+                                     self.b[L + 1], POS_OUT, 0, None, self.out)
         return self.out.view(B, SLOTS, 8)
 
     def backward(self):
@@ -160,14 +172,15 @@ class InitNet:
         B = self._B
         st = capi.stream_handle()
         L = len(CONV)
-        capi.dbmp_cnn_linear_backward_weight(st, self.h, self.dout, B, self.hidden, OUT,
+        R = B * POS
+        capi.dbmp_cnn_linear_backward_weight(st, self.h, self.dout, R, self.hidden, POS_OUT,
                                              self.gw[L + 1], self.gb[L + 1])
-        capi.dbmp_cnn_linear_backward_data(st, self.dout, B, OUT, self.wt[L + 1], self.hidden,
-                                           self.h, self.dh)
+        capi.dbmp_cnn_linear_backward_data(st, self.dout, R, POS_OUT, self.wt[L + 1],
+                                           self.hidden, self.h, self.dh)
         a6 = self.acts[-1]
-        capi.dbmp_cnn_linear_backward_weight(st, a6, self.dh, B, FLAT, self.hidden, self.gw[L],
+        capi.dbmp_cnn_linear_backward_weight(st, a6, self.dh, R, FEAT, self.hidden, self.gw[L],
                                              self.gb[L])
-        capi.dbmp_cnn_linear_backward_data(st, self.dh, B, self.hidden, self.wt[L], FLAT, a6,
+        capi.dbmp_cnn_linear_backward_data(st, self.dh, R, self.hidden, self.wt[L], FEAT, a6,
                                            self.dacts[-1])
         sizes = [IMG >> l for l in range(L)]  # input size of each conv layer
         for l in range(L - 1, -1, -1):

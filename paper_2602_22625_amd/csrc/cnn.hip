@@ -381,10 +381,12 @@ __global__ void __launch_bounds__(256) k_param_loss(const float *__restrict__ pr
 // template): decode  p = clip(t) * scale[q] + bias[q] + centre(slot, q),
 //          encode  t = clip((p - bias[q] - centre(slot, q)) / scale[q]),
 // where centre is the slot's cell centre for x (q = 0) and y (q = 1) and 0 otherwise, and clip
-// limits to [-clip, clip] every column but the angle (3).
+// limits to [-clip, clip] every column but the angle (3). Slots are numbered block by block
+// (block x block cells each, row-major inside; blocks row-major over the grid), so that the
+// 64 slots one position of the network's last feature map predicts are one 8 x 8 block.
 struct Coding {
     Col8 scale, bias;
-    int slots, grid;
+    int slots, grid, block;
     float cell, clip;
 };
 
@@ -395,8 +397,11 @@ __global__ void k_code(const float *__restrict__ in, long long n, Coding c, int 
     if (i >= n) return;
     const int q = (int)(i & 7);
     const int slot = (int)((i >> 3) % c.slots);
-    const float centre = q == 0 ? ((slot % c.grid) + 0.5f) * c.cell
-                                : (q == 1 ? ((slot / c.grid) + 0.5f) * c.cell : 0.f);
+    const int bb = c.block * c.block, blk = slot / bb, pos = slot - blk * bb;
+    const int bpr = c.grid / c.block;
+    const int col = (blk % bpr) * c.block + pos % c.block;
+    const int row = (blk / bpr) * c.block + pos / c.block;
+    const float centre = q == 0 ? (col + 0.5f) * c.cell : (q == 1 ? (row + 0.5f) * c.cell : 0.f);
     const float lim = q == 3 ? 3.0e38f : c.clip;
     if (decode) {
         const float t = fminf(fmaxf(in[i], -lim), lim);
@@ -535,10 +540,11 @@ int dbmp_cnn_param_loss(void *stream, const float *pred, const float *target,
 }
 
 int dbmp_cnn_code_params(void *stream, const float *in, long long n_rows, int slots, int grid,
-                         float cell, const float *scale8, const float *bias8, float clip,
-                         int decode, float *out)
+                         int block, float cell, const float *scale8, const float *bias8,
+                         float clip, int decode, float *out)
 {
-    if (!in || !out || !scale8 || !bias8 || n_rows < 0 || slots < 1 || grid < 1 || !(clip > 0.f))
+    if (!in || !out || !scale8 || !bias8 || n_rows < 0 || slots < 1 || grid < 1 || block < 1 ||
+        grid % block != 0 || !(clip > 0.f))
         return DBMP_CNN_EINVAL;
     for (int q = 0; q < 8; ++q)
         if (scale8[q] == 0.f) return DBMP_CNN_EINVAL;
@@ -550,6 +556,7 @@ int dbmp_cnn_code_params(void *stream, const float *in, long long n_rows, int sl
     }
     c.slots = slots;
     c.grid = grid;
+    c.block = block;
     c.cell = cell;
     c.clip = clip;
     const long long n = n_rows * 8;

@@ -284,8 +284,21 @@ def make_batch(n_images: int = 64, seed: int = 3000):
 # the GPU with torch generators (same recipe as target_image / init_params; different random
 # streams, so the values are not those of the NumPy generators).
 # --------------------------------------------------------------------------------------------
-SLOT_GRID = 32        # 32 x 32 cells: slot i starts in cell (i // 32, i % 32)
+SLOT_GRID = 32        # 32 x 32 cells, one per slot
+SLOT_BLOCK = 8        # slots are numbered block by block: 8 x 8 cells per block, blocks row-major
 SLOT_ATLAS_SEED = 4242
+
+
+def slot_cells(grid: int = SLOT_GRID, block: int = SLOT_BLOCK):
+    """(row, column) of the grid cell of every slot: slot i lies in block i // block^2 (blocks
+    in row-major order over the grid), at position i % block^2 of that block (row-major inside
+    it). block = 1 numbers the cells row-major."""
+    if grid % block:
+        raise ValueError("the block size must divide the grid")
+    i = np.arange(grid * grid)
+    b, j = i // (block * block), i % (block * block)
+    bpr = grid // block
+    return (b // bpr) * block + j // block, (b % bpr) * block + j % block
 
 
 def slot_atlas_index(n_slots: int, n_bitmaps: int) -> np.ndarray:
@@ -337,17 +350,19 @@ def target_images_torch(n: int, H: int, W: int, n_ellipses: int, seed: int, devi
 
 
 def slot_init_params_torch(n: int, H: int, W: int, log_s_mean: float, log_s_std: float,
-                           seed: int, device, grid: int = SLOT_GRID):
+                           seed: int, device, grid: int = SLOT_GRID, block: int = SLOT_BLOCK):
     """[n, grid*grid, 8] float32 initial parameters from the slot template: slot i starts at a
-    uniform point of grid cell i (stratified, so positions are still uniform over the image);
+    uniform point of its grid cell (slot_cells: stratified, so positions are still uniform over
+    the image);
     log_s ~ N(log_s_mean, log_s_std), theta ~ U[0, 2 pi), nu ~ N(0, 1), colour logits of
     U[1e-3, 1 - 1e-3]. The atlas index of slot i is slot_atlas_index()[i]."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     S = grid * grid
-    i = torch.arange(S, device=device)
-    gx, gy = (i % grid).float(), (i // grid).float()
+    rows, cols = slot_cells(grid, block)
+    gx = torch.tensor(cols, device=device, dtype=torch.float32)
+    gy = torch.tensor(rows, device=device, dtype=torch.float32)
     u = torch.rand(n, S, 6, generator=g, device=device)
     z = torch.randn(n, S, 2, generator=g, device=device)
     p = torch.empty(n, S, 8, device=device)

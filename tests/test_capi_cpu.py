@@ -53,10 +53,19 @@ def test_initialiser_host_argument_checks():
     assert lib.dbmp_cnn_param_loss(None, 16, 16, None, 16, 1.0, None, None, 16, None) == -1
     s8 = (ctypes.c_float * 8)(*([1.0] * 8))
     z8 = (ctypes.c_float * 8)(*([0.0] * 8))
-    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 8.0, ctypes.cast(z8, ctypes.c_void_p),
-                                    ctypes.cast(s8, ctypes.c_void_p), 4.0, 1, 16) == -1
-    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 8.0, ctypes.cast(s8, ctypes.c_void_p),
-                                    ctypes.cast(s8, ctypes.c_void_p), 0.0, 1, 16) == -1
+    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 1, ctypes.c_float(8.0),
+                                    ctypes.cast(z8, ctypes.c_void_p),
+                                    ctypes.cast(s8, ctypes.c_void_p), ctypes.c_float(4.0), 1,
+                                    16) == -1
+    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 1, ctypes.c_float(8.0),
+                                    ctypes.cast(s8, ctypes.c_void_p),
+                                    ctypes.cast(s8, ctypes.c_void_p), ctypes.c_float(0.0), 1,
+                                    16) == -1
+    # the block size must divide the grid
+    assert lib.dbmp_cnn_code_params(None, 16, 4, 16, 4, 3, ctypes.c_float(8.0),
+                                    ctypes.cast(s8, ctypes.c_void_p),
+                                    ctypes.cast(s8, ctypes.c_void_p), ctypes.c_float(4.0), 1,
+                                    16) == -1
     assert lib.dbmp_cnn_cast_weights(None, None, 1, 1, 1, None, None) == -1
 
 

@@ -183,19 +183,20 @@ def test_param_loss_added_gradient_and_no_target():
     assert np.allclose(dp.float().cpu().numpy(), x * np.array(xs), rtol=2 ** -8, atol=0)
 
 
-def test_code_params_matches_oracle():
+@pytest.mark.parametrize("block", [1, 8])
+def test_code_params_matches_oracle(block):
     g = np.random.default_rng(52)
     s8 = [8, 8, 0.5, 1, 2, 2, 2, 2]
     b8 = [0, 0, 2.48, 0, 0, 0, 0, 0]
     t = g.uniform(-6, 6, (3 * 1024, 8)).astype(np.float32)
     T = torch.tensor(t, device="cuda")
     out = torch.empty_like(T)
-    capi.dbmp_cnn_code_params(st(), T, t.shape[0], 1024, 32, 8.0, s8, b8, 4.0, 1, out)
+    capi.dbmp_cnn_code_params(st(), T, t.shape[0], 1024, 32, block, 8.0, s8, b8, 4.0, 1, out)
     torch.cuda.synchronize()
-    ref = co.code_params(t, 1024, 32, 8.0, s8, b8, 4.0, True)
+    ref = co.code_params(t, 1024, 32, block, 8.0, s8, b8, 4.0, True)
     assert np.allclose(out.cpu().numpy(), ref, rtol=1e-6, atol=1e-5)
     back = torch.empty_like(T)
-    capi.dbmp_cnn_code_params(st(), out, t.shape[0], 1024, 32, 8.0, s8, b8, 4.0, 0, back)
+    capi.dbmp_cnn_code_params(st(), out, t.shape[0], 1024, 32, block, 8.0, s8, b8, 4.0, 0, back)
     torch.cuda.synchronize()
-    ref2 = co.code_params(ref, 1024, 32, 8.0, s8, b8, 4.0, False)
+    ref2 = co.code_params(ref, 1024, 32, block, 8.0, s8, b8, 4.0, False)
     assert np.allclose(back.cpu().numpy(), ref2, rtol=1e-5, atol=1e-5)

@@ -57,19 +57,21 @@ def test_network_forward_backward_layer_by_layer():
         Wl = W[l].reshape(cout, 3, 3, cin)
         flips.append(_close_bf16(xs[l + 1], co.conv_forward(xs[l], Wl, Bs[l], relu=True)))
     B = 2
-    a6 = xs[-1].reshape(B, -1)
+    # the head runs on each of the 16 positions of the last feature map: rows of 256 features
+    R = B * ci.POS
+    a6 = xs[-1].reshape(R, ci.FEAT)
     h = _np(net.h)
     flips.append(_close_bf16(h, co.linear_forward(a6, W[L][:, 0, :], Bs[L], relu=True)))
     out = co.linear_forward(h, W[L + 1][:, 0, :], Bs[L + 1])
-    assert np.allclose(net.out.cpu().numpy(), out, rtol=1e-5, atol=1e-6)
+    assert np.allclose(net.out.cpu().numpy().reshape(R, -1), out, rtol=1e-5, atol=1e-6)
     _, G = co.param_loss(net.out.cpu().numpy().reshape(-1, 8),
                          codes.cpu().numpy().reshape(-1, 8), np.array(ci.LOSS_W),
                          1.0 / (B * ci.SLOTS))
-    dout = _np(net.dout)
-    assert np.allclose(dout, bf16r(G.reshape(B, -1)), rtol=2 ** -7, atol=1e-12)
+    dout = _np(net.dout).reshape(R, -1)
+    assert np.allclose(dout, bf16r(G.reshape(R, -1)), rtol=2 ** -7, atol=1e-12)
     dh = _np(net.dh)
     flips.append(_close_bf16(dh, co.linear_backward_data(dout, W[L + 1][:, 0, :], mask=h)))
-    flips.append(_close_bf16(ds[-1].reshape(B, -1),
+    flips.append(_close_bf16(ds[-1].reshape(R, -1),
                              co.linear_backward_data(dh, W[L][:, 0, :], mask=a6)))
 
     def rel(a, b):
@@ -92,16 +94,19 @@ def test_network_forward_backward_layer_by_layer():
     assert max(flips) < 0.01, flips
 
 
-def test_learned_start_gains_over_random_start():
-    """A small version of the whole procedure: 512 (target, 100-step fit) pairs, a short
-    training on the regression plus the image loss through the renderer, 8 held-out targets.
-    The trained network's start must beat the random start it replaces (initial PSNR), and
-    after the same number of Adam steps (50) the learned fit must be ahead of the plain one."""
+def test_learned_start_reaches_the_plain_psnr_sooner():
+    """The configured comparison on a scaled-down set: 1,024 (target, 500-step fit) pairs, a
+    short training on the regression plus the image loss through the renderer, then 8 held-out
+    targets, each fitted from the random start for 500 steps (the bar: its final PSNR, its wall
+    time) and from the network's start for at most 100 steps. The learned path (inference
+    included) must reach the bar in less wall time than the plain path on most targets, and its
+    start must beat the random start it replaces."""
     from paper_2602_22625_amd import cnn_init as ci
-    tg, fitted = ci.generate_pairs(512, steps=100, batch=256, seed=1)
+    tg, fitted = ci.generate_pairs(1024, steps=500, batch=256, seed=1)
     net = ci.InitNet(seed=0)
-    ci.train(net, tg, fitted, epochs=12, batch=64, lr=2e-3, image_weight=1.0)
-    res = ci.evaluate(net, n_targets=8, plain_steps=100, learned_steps=50, seed=10 ** 7)
+    ci.train(net, tg, fitted, epochs=30, batch=64, lr=2e-3, image_weight=16.0, param_weight=0.1)
+    res = ci.evaluate(net, n_targets=8, plain_steps=500, learned_steps=100, seed=10 ** 7)
     print({k: v for k, v in res.items() if k != "rows"})
-    assert res["median_psnr_cnn_start"] > res["median_psnr_random_start"] + 1.0
-    assert res["median_psnr_learned_end"] > res["median_psnr_plain_same_steps"]
+    assert res["median_psnr_cnn_start"] > res["median_psnr_random_start"] + 3.0
+    assert res["wins"] >= 6, res["wins"]
+    assert res["median_t_learned_ms"] < res["median_t_plain_ms"]

@@ -108,12 +108,32 @@ def test_code_params_round_trip_and_cell_centres():
     s8 = [8, 8, 0.5, 1, 2, 2, 2, 2]
     b8 = [0, 0, 2.5, 0, 0, 0, 0, 0]
     t = g.uniform(-3, 3, (2 * 16, 8))
-    p = co.code_params(t, 16, 4, 8.0, s8, b8, 4.0, True)
-    assert np.allclose(co.code_params(p, 16, 4, 8.0, s8, b8, 4.0, False), t, atol=1e-12)
-    # a zero code sits at the slot's cell centre with the mean scale
-    z = co.code_params(np.zeros((16, 8)), 16, 4, 8.0, s8, b8, 4.0, True)
+    p = co.code_params(t, 16, 4, 1, 8.0, s8, b8, 4.0, True)
+    assert np.allclose(co.code_params(p, 16, 4, 1, 8.0, s8, b8, 4.0, False), t, atol=1e-12)
+    # a zero code sits at the slot's cell centre with the mean scale (cells row-major)
+    z = co.code_params(np.zeros((16, 8)), 16, 4, 1, 8.0, s8, b8, 4.0, True)
     assert z[5, 0] == (5 % 4 + 0.5) * 8 and z[5, 1] == (5 // 4 + 0.5) * 8 and z[5, 2] == 2.5
     # clipping applies to every column but the angle
     big = np.full((1, 8), 10.0)
-    c = co.code_params(big, 16, 4, 8.0, s8, b8, 4.0, True)
+    c = co.code_params(big, 16, 4, 1, 8.0, s8, b8, 4.0, True)
     assert c[0, 3] == 10.0 and c[0, 4] == 8.0
+
+
+def test_code_params_block_order():
+    """Slots numbered 2 x 2 cells at a time on a 4 x 4 grid: slot 5 is the second cell (row 0,
+    column 1) of block 1 (the top-right block), i.e. cell (row 0, column 3); slot 13 is the
+    second cell of block 3 (bottom right): cell (2, 3). Every cell holds exactly one slot, and
+    the order is the one the slot template's generator lays out."""
+    s8 = [8, 8, 0.5, 1, 2, 2, 2, 2]
+    b8 = [0] * 8
+    z = co.code_params(np.zeros((16, 8)), 16, 4, 2, 8.0, s8, b8, 4.0, True)
+    assert (z[5, 0], z[5, 1]) == (3.5 * 8, 0.5 * 8)
+    assert (z[13, 0], z[13, 1]) == (3.5 * 8, 2.5 * 8)
+    cells = {(int(x // 8), int(y // 8)) for x, y in z[:, :2]}
+    assert len(cells) == 16
+    from paper_2602_22625_amd import synth
+    for grid, block in [(4, 2), (32, 8), (32, 1)]:
+        rows, cols = synth.slot_cells(grid, block)
+        zz = co.code_params(np.zeros((grid * grid, 8)), grid * grid, grid, block, 1.0, s8, b8,
+                            4.0, True)
+        assert np.array_equal(zz[:, 0] - 0.5, cols) and np.array_equal(zz[:, 1] - 0.5, rows)
