@@ -175,14 +175,17 @@ def main():
     ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--c4-pairs", type=int, default=10000)
     ap.add_argument("--c4-epochs", type=int, default=20)
     ap.add_argument("--cpu-window", type=int, default=160)
-    ap.add_argument("--profile", choices=["c0", "c1", "c2", "c4"], default=None,
+    ap.add_argument("--profile", choices=["c0", "c1", "c2", "c4", "cnn"], default=None,
                     help="profiling driver: `--steps` held fit steps of this workload, then the "
                          "separate forward and backward as often, then one 256 MiB device copy "
-                         "(the reference kernel that calibrates the HBM byte counters); prints "
-                         "nothing on stdout")
+                         "(the reference kernel that calibrates the HBM byte counters); with "
+                         "cnn, `--steps` training steps of the learned initialiser on a batch "
+                         "of 64 targets (regression loss only) and as many batched inferences; "
+                         "prints nothing on stdout")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures a single GPU; multi-GPU runs are not part of this build",
@@ -199,6 +202,9 @@ def main():
     capi.load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.profile == "cnn":
+        profile_cnn(args, synth, torch, dev)
+        return
     if args.profile:
         profile_driver(args, synth, capi, Fitter, Renderer, np, torch, dev)
         return
@@ -328,6 +334,10 @@ def main():
     if not args.no_c4:
         extra["c4_learned_init"] = bench_c4(args, torch)
 
+    # ---------------- the paper's ablation of its two helpers, on synthetic targets ------------
+    if not args.no_ablation:
+        extra["ablation_blur_sa_init"] = bench_ablation(synth, capi, Fitter, np, torch, dev)
+
     # ---------------- CPU baseline: the FP64 oracle on a window of the same workload -------------
     if not args.no_cpu_baseline:
         import oracle
@@ -356,6 +366,8 @@ def main():
 
 def bench_c3(args, synth, capi, autotune, BatchFitter, Fitter, np, torch, dev):
     import tempfile
+
+    from paper_2602_22625_amd.render import Renderer
     atlas3, items = synth.make_batch(64, seed=3000)
     A3 = torch.tensor(atlas3, device=dev)
     fits = [(torch.tensor(it["params"], device=dev), torch.tensor(it["idx"], device=dev),
@@ -380,6 +392,31 @@ def bench_c3(args, synth, capi, autotune, BatchFitter, Fitter, np, torch, dev):
     w3 = time.perf_counter() - t0
     bf.check()
     pairs3 = capi.dbmp_support_pairs(bf.R.ctx, capi.stream_handle(), reset=1)
+    psnr_batched = bf.psnrs()
+    # the plain path: the same 64 fits one after another, each its own Fitter (one-image
+    # launches, its own captured graph, the tuned tile size), over the same steps from the same
+    # start; only the steps are timed (each fit's sizing and capture are not)
+    R1 = Renderer(device=dev.index, check=False)
+    tile = best[0]
+    t_plain, psnr_plain = 0.0, []
+    for p_i, i_i, t_i in fits:
+        f = Fitter(p_i, i_i, A3, t_i, tile=tile, lr=1e-2, renderer=R1)
+        f.capture()
+        for _ in range(3):
+            f.step()
+        f.check()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps3):
+            f.step()
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        f.check()
+        psnr_plain.append(f.psnr())
+        del f
+    dpsnr = [abs(a - b) for a, b in zip(psnr_batched, psnr_plain)]
+    log("c3 plain path: %.3f ms per step of all 64 fits one after another (batched %.3f ms)"
+        % (1e3 * t_plain / steps3, 1e3 * w3 / steps3))
     grid16 = table.get("T16/grid")
     res = {
         "fits_x_steps_per_s": round(64 * steps3 / w3, 1),
@@ -391,6 +428,21 @@ def bench_c3(args, synth, capi, autotune, BatchFitter, Fitter, np, torch, dev):
         "tuning_ms_per_step_eager": {k: round(v * 1e3, 4) for k, v in table.items()},
         "speedup_vs_T16_grid_eager": round(grid16 / table[autotune.cfg_name(best)], 3)
         if grid16 else None,
+        "plain_path": {
+            "ms_per_step_all_fits": round(1e3 * t_plain / steps3, 4),
+            "fits_x_steps_per_s": round(64 * steps3 / t_plain, 1),
+            "batched_speedup": round(t_plain / w3, 3),
+            "mean_psnr_batched": round(float(np.mean(psnr_batched)), 4),
+            "mean_psnr_plain": round(float(np.mean(psnr_plain)), 4),
+            "max_abs_psnr_difference_db": round(max(dpsnr), 6),
+            "what": "the same 64 fits one after another, each a Fitter with its own graph "
+                    "(one image per launch, tile %d), the same steps from the same start" % tile,
+        },
+        "best_persistent": min(((k, v) for k, v in table.items() if "persistent" in k),
+                               key=lambda kv: kv[1])[0],
+        "best_persistent_vs_best": round(
+            min(v for k, v in table.items() if "persistent" in k) /
+            table[autotune.cfg_name(best)], 3),
     }
     log("c3: %.3f ms per batched step (64 fits), tuned %s" % (1e3 * w3 / steps3, best))
     del bf
@@ -470,6 +522,80 @@ def profile_driver(args, synth, capi, Fitter, Renderer, np, torch, dev):
     torch.cuda.synchronize()
     log("profile driver: %s, %d held fit steps, %d forward + MSE backward pairs, then a 256 MiB "
         "copy" % (args.profile, args.steps, args.steps))
+
+
+def bench_ablation(synth, capi, Fitter, np, torch, dev, steps=500):
+    """The paper's ablation of soft rasterisation (Gaussian blur of the atlas, sigma 1) and
+    structure-aware initialisation (window 7, base probability 0.1, opacity logit -4, colour
+    noise 0.02, as in its Table S1), on three synthetic scenarios: two 512x512 targets with
+    4,096 primitives and one 1024x1024 target with 16,384 primitives, 16 star/stroke bitmaps.
+    Every run is `steps` plain Adam steps (lr 1e-2) on MSE against a white background. Reported:
+    PSNR of the fit's own render (with the atlas it was fitted with), and for the blurred runs
+    also with the sharp atlas."""
+    import math
+
+    from paper_2602_22625_amd import aids
+    atlas = torch.tensor(synth.make_atlas("ss64x16"), device=dev)
+    blurred = aids.blur_atlas(atlas, 1.0)
+    scen = [("512x512 #1", 512, 64, 4096, 1101), ("512x512 #2", 512, 64, 4096, 1102),
+            ("1024x1024", 1024, 256, 16384, 1103)]
+    out = {}
+    for name, S, n_ell, N, seed in scen:
+        tgt = torch.tensor(synth.target_image(S, S, n_ell, seed), device=dev)
+        p_rand, idx = synth.init_params(N, S, S, math.log(12.0), 0.5, atlas.shape[0], seed + 500)
+        p_rand = torch.tensor(p_rand, device=dev)
+        idx = torch.tensor(idx, device=dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        p_sa, _, _ = aids.sa_init(tgt, N, 4.0, 24.0, nu_init=-4.0, sigma_c=0.02, win=7, base=0.1,
+                                  generator=gen)
+        rows = {}
+        for blur in (False, True):
+            for sa in (False, True):
+                f = Fitter(p_sa if sa else p_rand, idx, blurred if blur else atlas, tgt, lr=1e-2)
+                f.capture(10)
+                f.run(steps, check_every=steps)
+                f._render()
+                f.R.backward_mse(f.target, None, out=f.grad, accumulate=True)
+                own = f.psnr()
+                row = {"psnr": round(own, 3)}
+                if blur:
+                    sharp = Fitter(f.params, idx, atlas, tgt)
+                    sharp._size()
+                    sharp._render()
+                    sharp.R.backward_mse(sharp.target, None, out=sharp.grad, accumulate=True)
+                    row["psnr_sharp_atlas"] = round(sharp.psnr(), 3)
+                    del sharp
+                rows["%s blur, %s SA-init" % ("with" if blur else "no",
+                                             "with" if sa else "no")] = row
+                del f
+        out[name] = rows
+        log("ablation %s: %s" % (name, {k: v["psnr"] for k, v in rows.items()}))
+    out["note"] = ("synthetic stand-ins for the paper's three scenarios (its targets are not "
+                   "available); plain Adam lr 1e-2 for %d steps in every row" % steps)
+    return out
+
+
+def profile_cnn(args, synth, torch, dev):
+    """`--steps` training steps of the initialiser network on 64 targets (regression on the
+    slot template's parameters) and `--steps` inferences of the same batch: the MFMA layer
+    kernels alone, for a kernel trace."""
+    from paper_2602_22625_amd import cnn_init as ci
+    B = 64
+    img = synth.target_images_torch(B, ci.IMG, ci.IMG, 8, 5, dev)
+    fitted = synth.slot_init_params_torch(B, ci.IMG, ci.IMG, ci.LOG_S_MEAN, ci.LOG_S_STD, 6, dev)
+    codes = ci.encode(fitted)
+    net = ci.InitNet(seed=0)
+    for _ in range(args.steps):
+        net.train_step(img, codes, 2e-3)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        net.forward(img)
+    torch.cuda.synchronize()
+    log("profile driver: cnn, %d training steps and %d inferences of %d images; %.3f GFLOP per "
+        "training step, %.3f GFLOP per inference (matrix-core work as executed)"
+        % (args.steps, args.steps, B, B * ci.train_flops_per_image() * 1e-9,
+           B * ci.forward_flops_per_image() * 1e-9))
 
 
 if __name__ == "__main__":

@@ -80,6 +80,38 @@ def decode(codes):
 
 
 # ------------------------------------------------------------------------------------------
+# Matrix-core work per image, as the layer kernels execute it (for the roofline): each layer is
+# one implicit GEMM of 2 M N K FLOP; the first layer's input carries 8 channels (3 used), and
+# the input gradient of a stride-2 convolution runs over every input pixel and all 9 taps (a
+# tap that does not reach the pixel contributes zeros).
+# ------------------------------------------------------------------------------------------
+def _layer_gemms():
+    """[(kind, M, N, K)] per image for the forward, input-gradient and weight-gradient GEMMs."""
+    fwd, bwd = [], []
+    s = IMG
+    for l, (ci, co) in enumerate(CONV):
+        o = s // 2
+        fwd.append((o * o, co, 9 * ci))
+        bwd.append((co, 9 * ci, o * o))          # weight gradient
+        if l > 0:
+            bwd.append((s * s, ci, 9 * co))      # input gradient
+        s = o
+    fwd += [(POS, HIDDEN, FEAT), (POS, POS_OUT, HIDDEN)]
+    bwd += [(POS_OUT, HIDDEN, POS), (POS, HIDDEN, POS_OUT),   # output layer: weight, input
+            (HIDDEN, FEAT, POS), (POS, FEAT, HIDDEN)]         # hidden layer: weight, input
+    return fwd, bwd
+
+
+def forward_flops_per_image():
+    return float(sum(2 * m * n * k for m, n, k in _layer_gemms()[0]))
+
+
+def train_flops_per_image():
+    fwd, bwd = _layer_gemms()
+    return float(sum(2 * m * n * k for m, n, k in fwd + bwd))
+
+
+# ------------------------------------------------------------------------------------------
 # Network
 # ------------------------------------------------------------------------------------------
 class InitNet:

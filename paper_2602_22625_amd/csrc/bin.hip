@@ -32,6 +32,9 @@ k_setup(const TexT *__restrict__ atlas, int B, int Hb, int Wb, TexT *__restrict_
         int *__restrict__ box)
 {
     const int Hp = Hb + 2;
+    if (blockIdx.x == 0)  // the two zero rows after the last bitmap (the all-zero cell)
+        for (int i = threadIdx.x; i < 2 * Wp; i += SETUP_THREADS)
+            pad[(size_t)B * Hp * Wp + i] = TexT(0);
     {
         const int b = blockIdx.x;
         const TexT *src = atlas + (size_t)b * Hb * Wb;

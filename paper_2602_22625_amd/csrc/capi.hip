@@ -150,7 +150,8 @@ int set_atlas_impl(dbmp_ctx *c, hipStream_t st, const void *atlas, int B, int Hb
         return fail(c, DBMP_EINVAL, "atlas too large (the padded copy must stay below 4 GiB)");
     c->atlas_valid = false;  // until the new copy is enqueued (a failed growth frees the old one)
     int rc;
-    if ((rc = ensure(c, c->atlas_pad, esz * (size_t)B * Hp * Wp, st, "atlas"))) return rc;
+    if ((rc = ensure(c, c->atlas_pad, esz * (size_t)padded_atlas_elems(B, Hb, Wb), st, "atlas")))
+        return rc;
     if ((rc = ensure(c, c->box, 16 * (size_t)B, st, "boxes"))) return rc;
     BinArgs ba{};
     ba.atlas = atlas; ba.dtype = dtype; ba.B = B; ba.Hb = Hb; ba.Wb = Wb; ba.Wp = Wp;
@@ -292,6 +293,7 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.imgs = (const ImgDev *)c->imgs.p;
     ra.n_images = (int)ni; ra.n_tiles = (int)tiles;
     ra.atlas_pad = c->atlas_pad.p; ra.dtype = dtype; ra.Wp = Wp; ra.Hb = Hb; ra.Wb = Wb;
+    ra.zcell = (int)zero_cell(B, Hb, Wb);
     ra.bg = bg; ra.bg_pp = bg_pp; ra.image = image; ra.alpha = alpha;
     ra.saveK = (int *)c->saveK.p; ra.saveT = (float *)c->saveT.p;
     ra.flags = (const int *)c->flags.p; ra.TS = tile;

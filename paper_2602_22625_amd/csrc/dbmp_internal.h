@@ -141,6 +141,7 @@ struct RasterArgs {
     int n_images, n_tiles;
     const void *atlas_pad;
     int dtype, Wp, Hb, Wb;
+    int zcell;                         // element offset of the padded atlas's all-zero cell
     const float *bg;
     int bg_pp;
     float *image, *alpha;

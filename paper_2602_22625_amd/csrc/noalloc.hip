@@ -12,6 +12,7 @@
 // written before it is read within the call.
 #include "dbmp_internal.h"
 #include "diffbmp.h"
+#include "workspace.h"
 
 #include <limits.h>
 
@@ -81,7 +82,7 @@ Layout layout(long long N, int B, int Hb, int Wb, size_t esz, long long n_tiles,
     L.list_max = take(4 * (size_t)DBMP_COUNTER_SLOTS);
     L.counter = take(8 * (size_t)DBMP_COUNTER_SLOTS);
     L.box = take(16 * (size_t)B);
-    L.atlas = take(esz * (size_t)B * (Hb + 2) * (Wb + 2));
+    L.atlas = take(esz * (size_t)padded_atlas_elems(B, Hb, Wb));
     L.recs = take(sizeof(PrimRec) * (size_t)N);
     L.lists = take(4 * (size_t)n_tiles * (size_t)cap);
     L.saveK = take(4 * (size_t)n_pix);
@@ -121,8 +122,7 @@ extern "C" int dbmp_render_mse_noalloc(dbmp_stream stream, const float *params,
     if (tile != 8 && tile != 16 && tile != 32) return DBMP_EINVAL;
     if (list_capacity < 1 || list_capacity >= (1 << 24)) return DBMP_EINVAL;
     const size_t esz = atlas_dtype == DBMP_F32 ? 4 : 2;
-    const long long elems = (long long)B * (Hb + 2) * (Wb + 2);
-    if (elems >= INT_MAX || elems * (long long)esz >= (1LL << 32)) return DBMP_EINVAL;
+    if (!atlas_addressable(B, Hb, Wb, (long long)esz)) return DBMP_EINVAL;
     const int cap = (list_capacity + 31) & ~31;
     const int ntx = (W + tile - 1) / tile, nty = (H + tile - 1) / tile;
     const long long n_tiles = (long long)ntx * nty;
@@ -176,6 +176,7 @@ extern "C" int dbmp_render_mse_noalloc(dbmp_stream stream, const float *params,
     ra.imgs = d_img;
     ra.n_images = 1; ra.n_tiles = (int)n_tiles;
     ra.atlas_pad = S + L.atlas; ra.dtype = atlas_dtype; ra.Wp = Wb + 2; ra.Hb = Hb; ra.Wb = Wb;
+    ra.zcell = (int)zero_cell(B, Hb, Wb);
     ra.bg = bg; ra.bg_pp = bg_per_pixel ? 1 : 0; ra.image = image; ra.alpha = nullptr;
     ra.saveK = (int *)(S + L.saveK); ra.saveT = (float *)(S + L.saveT);
     ra.flags = status; ra.TS = tile;

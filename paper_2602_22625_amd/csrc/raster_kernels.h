@@ -31,7 +31,8 @@
 // gfx950's cross-row lane swaps (v_permlane32_swap, v_permlane16_swap) and DPP row/quad
 // permutes, after which lane 8q holds the wave total of factor q; eight lanes add them into the
 // workgroup's per-entry LDS sums, which after each batch are scaled by the primitive's constant
-// factors and flushed with one float32 atomic per (tile entry, parameter).
+// factors and flushed with one float32 atomic per (tile entry, parameter). Since g is fixed per
+// pixel, the walk carries only the scalar g . G of the composite behind each layer.
 //
 // Each walk comes in two builds (LAUNCH below): one texel cell in flight, or two, where the
 // next visited entry's texels are requested before the current entry is processed.
@@ -128,21 +129,25 @@ struct Cell {
     float wu, wv;             // fractional position inside the cell
 };
 
-// A lane outside the support (in = false) reads the padded bitmap's corner cell (0, 0) with zero
-// weights: only the zero border enters, so M = MU = MV = 0 there exactly. The cell is addressed
-// by its 32-bit byte offset from the atlas base (atlases are far below 4 GB): the loads take the
-// base from scalar registers and only the offset per lane, and the offset costs one 24-bit
-// multiply-add (texel coordinates and row pitches are below 2^24). Inside the support
-// U', V' >= 0: the texel index is the truncation.
+// A lane outside the support (in = false) reads the all-zero cell that follows the padded
+// atlas (element offset zcell), so M = MU = MV = 0 there exactly whatever its weights: one
+// select of the address, no select of the weights. The cell is addressed by its 32-bit byte
+// offset from the atlas base (atlases are below 4 GB): the loads take the base from scalar
+// registers and only the offset per lane, and the offset costs one 24-bit multiply-add (texel
+// coordinates and row pitches are below 2^24). Inside the support U', V' >= 0: the texel index
+// is the truncation.
 // PIN (pipelined walks): the loads stay where they are issued, ahead of the other cell's
 // arithmetic, instead of being moved down to their first use by the compiler.
 template <typename TexT, bool PIN>
 __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restrict__ atlas,
-                                             int tex, int Wp, double U, double V, bool in)
+                                             int tex, int Wp, double U, double V, bool in,
+                                             int zcell)
 {
-    c.wu = in ? (float)__builtin_amdgcn_fract(U) : 0.f;
-    c.wv = in ? (float)__builtin_amdgcn_fract(V) : 0.f;
-    const unsigned cell = in ? __umul24((unsigned)(int)V, (unsigned)Wp) + (unsigned)(int)U : 0u;
+    c.wu = (float)__builtin_amdgcn_fract(U);
+    c.wv = (float)__builtin_amdgcn_fract(V);
+    const unsigned at = in ? (unsigned)tex + __umul24((unsigned)(int)V, (unsigned)Wp) +
+                                 (unsigned)(int)U
+                           : (unsigned)zcell;
     // The atlas is a read-only kernel argument, so the compiler takes loads from it as
     // movable anywhere; seen through this (empty) statement the base is an ordinary pointer,
     // and the loads stay ahead of the statement at the end.
@@ -150,7 +155,7 @@ __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restri
     using GTex = const __attribute__((address_space(1))) TexT;
     GChar *base = (GChar *)atlas;
     if constexpr (PIN) asm volatile("" : "+s"(base));
-    const unsigned b0 = ((unsigned)tex + cell) * (unsigned)sizeof(TexT);
+    const unsigned b0 = at * (unsigned)sizeof(TexT);
     GTex *t0 = (GTex *)(base + b0);
     GTex *t1 = (GTex *)(base + (b0 + (unsigned)Wp * sizeof(TexT)));
     c.p00 = t0[0];
@@ -334,7 +339,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          PrimRec *__restrict__ s_rec,
                                          float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
-                                         const TexT *__restrict__ atlas, int Wp,
+                                         const TexT *__restrict__ atlas, int Wp, int zcell,
                                          const TileGeom<TS> &tg, uint64_t vmask, float g0,
                                          float g1, float g2, float ga, float G0, float G1,
                                          float G2, int K, float TK, float *__restrict__ dparams,
@@ -346,7 +351,7 @@ __global__ void __launch_bounds__(TS * TS)
 k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
              int *__restrict__ tile_count, int *__restrict__ tile_len, int *__restrict__ list_max,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
-             const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
+             const TexT *__restrict__ atlas, int Wp, int zcell, const float *__restrict__ bg,
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
              float *__restrict__ saveT, const int *__restrict__ flags,
              unsigned long long *__restrict__ pair_counter, int sched, int grab,
@@ -459,7 +464,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
             double U = 0.0, V = 0.0;
             const int e = find(hits, U, V, m);
             request_cell<TexT, true>(c, atlas, e >= 0 ? s_rec[e].tex : 0, Wp, U, V,
-                                     __builtin_amdgcn_inverse_ballot_w64(m));
+                                     __builtin_amdgcn_inverse_ballot_w64(m), zcell);
             return e;
         };
         // The pipelined walk composites on every lane (no branch, so the wait for a cell's
@@ -509,7 +514,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                         npairs += __popcll(m);
                         if (__builtin_amdgcn_inverse_ballot_w64(m)) {  // the support lanes only
                             Cell<TexT> c;
-                            request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V, true);
+                            request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V, true, zcell);
                             float M, MU, MV;
                             blend<TexT>(c, M, MU, MV);
                             const float a = r.ka * M;  // Eq. (3)
@@ -569,12 +574,14 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
             bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return s_ids[j]; }, staged, s_rec,
                                             s_grad,
                                       recs,
-                                      atlas, Wp, tg, vmask, g0, g1, g2, 0.f, b0, b1, b2,
+                                      atlas, Wp, zcell, tg, vmask, g0, g1, g2, 0.f, b0, b1,
+                                      b2,
                                       tg.valid ? K : -1, TK, dparams, cu1, cv1, cu_cv, cv_cu,
                                       lane);
         else
             bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return ((volatile int *)seg)[j]; },
-                                      staged, s_rec, s_grad, recs, atlas, Wp, tg, vmask, g0,
+                                      staged, s_rec, s_grad, recs, atlas, Wp, zcell, tg, vmask,
+                                      g0,
                                       g1, g2,
                                       0.f, b0, b1, b2, tg.valid ? K : -1, TK, dparams, cu1, cv1,
                                       cu_cv, cv_cu, lane);
@@ -609,13 +616,16 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 //     s4 = sum dal M                         nu:       k_a (1 - sigma) s4 (kaom)
 //     s5..s7 = sum g_c T_j alpha_j           colours:  c (1 - c) s5..s7
 // with dal = dL/dalpha_j, U_c, V_c the bitmap coordinates about the centre and r the ratio of the
-// bitmap's half-extents.
+// bitmap's half-extents. Each lane centres its coordinates (float64 subtraction, then the
+// conversion): summing the uncentred coordinates and subtracting cu1 s0 + cv1 s1 at the flush
+// instead saves two instructions but cancels, and it was measured to lose about two decimal
+// digits on the angle's gradient.
 template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, typename IdAt>
 __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          PrimRec *__restrict__ s_rec,
                                          float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
-                                         const TexT *__restrict__ atlas, int Wp,
+                                         const TexT *__restrict__ atlas, int Wp, int zcell,
                                          const TileGeom<TS> &tg, uint64_t vmask, float g0,
                                          float g1, float g2, float ga, float G0, float G1,
                                          float G2, int K, float TK, float *__restrict__ dparams,
@@ -624,10 +634,13 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
 {
     const double xd = tg.px, yd = tg.py;
     float Bk = 1.f, Trun = 0.f;  // behind K the transmittance is 0
+    // g is fixed per pixel, so the walk carries only the projection gG = g . G of the composite
+    // behind the current layer (G starts at the background and advances as G + alpha (c - G))
+    float gG = fmaf(g2, G2, fmaf(g1, G1, g0 * G0));
     // Pipelined walk: the next staged entry (descending list order: back to front) that a lane
-    // of this wave lies in, or -1; its cell is requested for every lane (for entry -1: any valid
-    // bitmap, all weights zero), with the bitmap coordinates about the centre that the
-    // geometric gradients use.
+    // of this wave lies in, or -1; its cell is requested for every lane (for entry -1, and for
+    // lanes outside the support, the all-zero cell), with the bitmap coordinates about the
+    // centre that the geometric gradients use.
     auto find = [&](uint64_t &hits, Cell<TexT> &c, float &Uc, float &Vc) {
         int e = -1;
         double U = 0.0, V = 0.0;
@@ -642,7 +655,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             if (msk != 0) { e = k; break; }
         }
         request_cell<TexT, true>(c, atlas, e >= 0 ? s_rec[e].tex : 0, Wp, U, V,
-                                 __builtin_amdgcn_inverse_ballot_w64(msk));
+                                 __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
         Uc = (float)(U - cu1);
         Vc = (float)(V - cv1);
         return e;
@@ -665,12 +678,10 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
         rc = fmaf(rc, fmaf(-mc, rc, 1.f), rc);
         const float Tj = j == K ? TK : Trun * rc;
         Trun = Tj;
-        // c_j - G: the colour's lead over the composite behind it, which also advances G to the
-        // composite behind layer j - 1: G + alpha (c - G) = alpha c + (1 - alpha) G
-        const float e0 = r.cr - G0, e1 = r.cg - G1, e2 = r.cb - G2;
-        float dal = g0 * e0;
-        dal = fmaf(g1, e1, dal);
-        dal = fmaf(g2, e2, dal);
+        // g . (c_j - G): the colour's lead over the composite behind it, which also advances
+        // g . G to the composite behind layer j - 1: g . (G + alpha (c - G))
+        const float lead = fmaf(g2, r.cb, fmaf(g1, r.cg, g0 * r.cr)) - gG;
+        float dal = lead;
         if (HAS_GA) dal = fmaf(ga, Bk, dal);
         dal *= Tj;
         const float ta = Tj * a;
@@ -683,10 +694,12 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
         d[1] = gV;
         d[2] = fmaf(gU, Ub, gV * Vb);
         d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
-        G0 = fmaf(a, e0, G0);
-        G1 = fmaf(a, e1, G1);
-        G2 = fmaf(a, e2, G2);
+        gG = fmaf(a, lead, gG);
         Bk *= m;
+        // lane 8q holds the wave total of value q; eight lanes add into the entry's LDS slots.
+        // (Stopping the butterfly after the row mirror and letting all 64 lanes add their
+        // partials, 8 lanes per address, saves 4 instructions but serialised in the LDS atomic
+        // unit: it made the 2048^2 fit step's raster launch twice as long.)
         const float tot = reduce8(d, lane);
         if ((lane & 7) == 0)
             __hip_atomic_fetch_add(s_grad + e * 8 + (lane >> 3), tot, __ATOMIC_RELAXED,
@@ -724,7 +737,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                 if (msk == 0) continue;
                 Cell<TexT> c;
                 request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V,
-                                          __builtin_amdgcn_inverse_ballot_w64(msk));
+                                          __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
                 under(e, b0 + e, c, (float)(U - cu1), (float)(V - cv1));
             }
         }
@@ -755,7 +768,7 @@ __global__ void __launch_bounds__(TS * TS)
 k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, int list_cap,
              const int *__restrict__ tile_len,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
-             const TexT *__restrict__ atlas, int Wp, const float *__restrict__ bg,
+             const TexT *__restrict__ atlas, int Wp, int zcell, const float *__restrict__ bg,
              const int *__restrict__ saveK, const float *__restrict__ saveT,
              const float *__restrict__ gI, const float *__restrict__ target,
              float *__restrict__ loss_tile, const float *__restrict__ gA,
@@ -806,7 +819,8 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
         bwd_walk<TS * TS, TexT, HAS_GA, PIPE>(n, [&](int j) { return seg[j]; }, false, s_rec,
                                               s_grad,
                                         recs,
-                                        atlas, Wp, tg, vmask, g0, g1, g2, ga, G0, G1, G2, K, TK,
+                                        atlas, Wp, zcell, tg, vmask, g0, g1, g2, ga, G0, G1, G2,
+                                        K, TK,
                                         dparams, cu1, cv1, cu_cv, cv_cu, lane);
         if (MSE) {
             const float ws = wave_sum(sq);
@@ -837,15 +851,38 @@ static void launch_kernel(K kern, int grid, int block, hipStream_t st, hipEvent_
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, args...);
 }
 
+// Workgroups of a kernel that one compute unit holds at once (registers and LDS permitting).
+// A persistent grid larger than what is resident would leave its surplus workgroups waiting
+// for others to finish, and their whole share of the tiles would run after them.
+template <typename K>
+static int resident_per_cu(K kern, int threads)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
+// The persistent grid: the schedule's workgroups per compute unit, at most what is resident.
+template <typename K>
+static int persistent_grid(K kern, int threads, const RasterArgs &a)
+{
+    static const int resident = resident_per_cu(kern, threads);
+    return std::min(std::min(a.grid, a.n_cu * resident), a.n_tiles);
+}
+
 template <int TS, typename TexT, bool BGPP, bool FUSED, int LAUNCH>
 static void fwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
-    const int grid = LAUNCH == LAUNCH_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
+    const int grid = LAUNCH == LAUNCH_PERSISTENT
+                         ? persistent_grid(k_raster_fwd<TS, TexT, BGPP, FUSED, LAUNCH>, TS * TS, a)
+                         : a.n_tiles;
     launch_kernel(k_raster_fwd<TS, TexT, BGPP, FUSED, LAUNCH>, grid, TS * TS, st, a.ev_start,
         a.ev_stop, a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len,
         a.list_max, a.imgs,
-        a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.bg, a.image, a.alpha, a.saveK,
+        a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.zcell, a.bg, a.image, a.alpha,
+        a.saveK,
         a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue, a.target,
         a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu),
         a.fit_state);
@@ -855,10 +892,13 @@ template <int TS, typename TexT, bool BGPP, bool GA, bool MSE, int LAUNCH>
 static void bwd_t(const RasterArgs &a, hipStream_t st)
 {
     const double cu = 0.5 * (a.Wb - 1), cv = 0.5 * (a.Hb - 1);
-    const int grid = LAUNCH == LAUNCH_PERSISTENT ? std::min(a.grid, a.n_tiles) : a.n_tiles;
+    const int grid = LAUNCH == LAUNCH_PERSISTENT
+                         ? persistent_grid(k_raster_bwd<TS, TexT, BGPP, GA, MSE, LAUNCH>, TS * TS, a)
+                         : a.n_tiles;
     launch_kernel(k_raster_bwd<TS, TexT, BGPP, GA, MSE, LAUNCH>, grid, TS * TS, st, a.ev_start,
         a.ev_stop, a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
-        (const TexT *)a.atlas_pad, a.Wp, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI, a.target,
+        (const TexT *)a.atlas_pad, a.Wp, a.zcell, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI,
+        a.target,
         a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
         (float)(cv / cu), a.flags, a.sched, a.grab, a.order, a.queue + 2);
 }

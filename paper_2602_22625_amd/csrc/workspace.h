@@ -58,10 +58,24 @@ int grow_buffer(Buf &b, size_t bytes, bool must_be_zero, Ops &ops, bool *grown)
 // Whether the raster kernels can address a padded atlas of B bitmaps of (Hb + 2) x (Wb + 2)
 // texels of `esz` bytes: a texel is reached by a 32-bit unsigned byte offset from the atlas
 // base, and a bitmap's first texel by an int element offset.
+// Elements of the padded atlas: B bitmaps of (Hb + 2) x (Wb + 2) (a one-texel zero border),
+// then two zero rows of Wb + 2 texels, which hold an all-zero bilinear cell (zero_cell).
+inline long long padded_atlas_elems(long long B, long long Hb, long long Wb)
+{
+    return B * (Hb + 2) * (Wb + 2) + 2 * (Wb + 2);
+}
+
+// Element offset of that all-zero cell: a lane outside a primitive's support samples it, so its
+// M and derivatives are exactly zero whatever its weights.
+inline long long zero_cell(long long B, long long Hb, long long Wb)
+{
+    return B * (Hb + 2) * (Wb + 2);
+}
+
 inline bool atlas_addressable(long long B, long long Hb, long long Wb, long long esz)
 {
     if (B < 1 || Hb < 2 || Wb < 2 || (esz != 2 && esz != 4)) return false;
-    const long long elems = B * (Hb + 2) * (Wb + 2);
+    const long long elems = padded_atlas_elems(B, Hb, Wb);
     return elems < 2147483647LL && elems * esz < 4294967296LL;
 }
 
