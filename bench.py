@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--c4-pairs", type=int, default=10000)
     ap.add_argument("--c4-epochs", type=int, default=20)
-    ap.add_argument("--cpu-window", type=int, default=160)
+    ap.add_argument("--cpu-window", type=int, default=192)
     ap.add_argument("--profile", choices=["c0", "c1", "c2", "c4", "cnn"], default=None,
                     help="profiling driver: `--steps` held fit steps of this workload, then the "
                          "separate forward and backward as often, then one 256 MiB device copy "

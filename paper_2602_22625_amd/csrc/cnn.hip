@@ -46,11 +46,18 @@ __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((uint32_t)
 // ------------------------------------------------------------------------------------------
 constexpr int BM = 64, BN = 64, BK = 32, NT = 256, LDK = BK + 8;
 
-// Operand loaders. VEC: elements (row, k .. k+7) are contiguous (one 16-byte load, thread t
-// loads row t/4, k chunk (t%4)*8); otherwise 8 scalar loads along K (thread t loads row t%64,
-// k chunk (t/64)*8, so a wave reads 64 consecutive rows: coalesced when rows are contiguous).
+// Operand loaders, by how their elements lie in memory:
+//   VEC   elements (row, k .. k+7) are contiguous: one 16-byte load (thread t loads row t/4,
+//         k chunk (t%4)*8);
+//   TVEC  elements (row .. row+7, k) are contiguous (an operand read across K whose rows run
+//         along memory, e.g. NHWC channels): one 16-byte load (thread t loads k t/8, row chunk
+//         (t%8)*8), written into the K-contiguous LDS tile transposed, 8 two-byte stores;
+//   SCAL  8 scalar loads along K (thread t loads row t%64, k chunk (t/64)*8, so a wave reads 64
+//         consecutive rows): the fallback for row counts or pitches that are not multiples of 8.
+enum { SCAL = 0, VEC = 1, TVEC = 2 };
+
 struct LPlain {  // element (row, k) = p[row * ld + k]
-    static constexpr bool VEC = true;
+    static constexpr int KIND = VEC;
     const u16 *p;
     int ld, R, K;
     __device__ uint4 load8(int row, int k) const
@@ -60,10 +67,21 @@ struct LPlain {  // element (row, k) = p[row * ld + k]
     }
 };
 
-struct LTrans {  // element (row, k) = p[k * ld + row]
-    static constexpr bool VEC = false;
+template <int KD>
+struct LTrans {  // element (row, k) = p[k * ld + row]; TVEC needs ld % 8 == 0
+    static constexpr int KIND = KD;
     const u16 *p;
     int ld, R, K;
+    __device__ uint4 load8t(int row, int k) const  // rows row .. row+7 at k (row % 8 == 0)
+    {
+        if (k >= K || row >= R) return make_uint4(0, 0, 0, 0);
+        if (row + 8 <= R) return *reinterpret_cast<const uint4 *>(p + (size_t)k * ld + row);
+        u16 e[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = row + i < R ? p[(size_t)k * ld + row + i] : 0;
+        return make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
+                          e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
+    }
     __device__ u16 load1(int row, int k) const
     {
         if (row >= R || k >= K) return 0;
@@ -72,7 +90,7 @@ struct LTrans {  // element (row, k) = p[k * ld + row]
 };
 
 struct LIm2col {  // row = output pixel (b, oy, ox), k = (ky, kx, ic); x NHWC [B][H][W][C]
-    static constexpr bool VEC = true;
+    static constexpr int KIND = VEC;
     const u16 *x;
     int H, W, C, OH, OW, M, K;
     __device__ uint4 load8(int m, int k) const
@@ -89,7 +107,7 @@ struct LIm2col {  // row = output pixel (b, oy, ox), k = (ky, kx, ic); x NHWC [B
 };
 
 struct LCol2im {  // row = input pixel (b, y, x), k = (ky, kx, oc); dz NHWC [B][OH][OW][Co]
-    static constexpr bool VEC = true;
+    static constexpr int KIND = VEC;
     const u16 *dz;
     int H, W, Co, OH, OW, M, K;
     __device__ uint4 load8(int m, int k) const
@@ -107,10 +125,22 @@ struct LCol2im {  // row = input pixel (b, y, x), k = (ky, kx, oc); dz NHWC [B][
     }
 };
 
+template <int KD>
 struct LIm2colT {  // row = (ky, kx, ic), k = output pixel (b, oy, ox); x NHWC [B][H][W][C]
-    static constexpr bool VEC = false;
+    static constexpr int KIND = KD;  // TVEC needs C % 8 == 0 (8 rows share one tap)
     const u16 *x;
     int H, W, C, OH, OW, R, K;
+    __device__ uint4 load8t(int n, int k) const  // rows n .. n+7 at k (n % 8 == 0)
+    {
+        if (n >= R || k >= K) return make_uint4(0, 0, 0, 0);
+        const int tap = n / C, ic = n - tap * C;
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        const int b = k / (OH * OW), r = k - b * OH * OW;
+        const int oy = r / OW, ox = r - oy * OW;
+        const int iy = 2 * oy + ky - 1, ix = 2 * ox + kx - 1;
+        if (iy < 0 || iy >= H || ix < 0 || ix >= W) return make_uint4(0, 0, 0, 0);
+        return *reinterpret_cast<const uint4 *>(x + (((size_t)b * H + iy) * W + ix) * C + ic);
+    }
     __device__ u16 load1(int n, int k) const
     {
         if (n >= R || k >= K) return 0;
@@ -165,8 +195,10 @@ struct EAdd {  // out += acc (float atomics: split-K partial sums)
 template <class L>
 __device__ __forceinline__ void fetch(const L &l, int row0, int k0, uint4 &v)
 {
-    if constexpr (L::VEC) {
+    if constexpr (L::KIND == VEC) {
         v = l.load8(row0 + (int)(threadIdx.x >> 2), k0 + (int)(threadIdx.x & 3) * 8);
+    } else if constexpr (L::KIND == TVEC) {
+        v = l.load8t(row0 + (int)(threadIdx.x & 7) * 8, k0 + (int)(threadIdx.x >> 3));
     } else {
         const int row = row0 + (int)(threadIdx.x & 63), k = k0 + (int)(threadIdx.x >> 6) * 8;
         u16 e[8];
@@ -183,7 +215,16 @@ template <class L>
 __device__ __forceinline__ void stash(u16 *s, const uint4 &v)
 {
     int row, kc;
-    if constexpr (L::VEC) {
+    if constexpr (L::KIND == TVEC) {  // 8 rows at one k: transposed into the K-contiguous tile
+        row = (threadIdx.x & 7) * 8;
+        kc = threadIdx.x >> 3;
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            s[(row + j) * LDK + kc] = (u16)(w[j >> 1] >> ((j & 1) * 16));
+        return;
+    }
+    if constexpr (L::KIND == VEC) {
         row = threadIdx.x >> 2;
         kc = (threadIdx.x & 3) * 8;
     } else {
@@ -278,7 +319,48 @@ static int splits_for(int M, int N, int K)
 // ------------------------------------------------------------------------------------------
 // Elementwise kernels
 // ------------------------------------------------------------------------------------------
-// Column sums of a bf16 matrix [M][N] added into out[N] (bias gradients).
+// Column sums of a bf16 matrix [M][N] added into out[N] (bias gradients), N % 8 == 0 and
+// N <= 2048: with G = N / 8 column groups, thread t reads the 8 columns of group t % G (one
+// 16-byte load) in every (256 / G)-th row of the workgroup's rows; the partial sums meet in LDS
+// and each column gets one float atomic per workgroup.
+__global__ void __launch_bounds__(256) k_colsum8(const u16 *__restrict__ z, int M, int N,
+                                                 int rows_per_block, float *__restrict__ out)
+{
+    const int G = N >> 3, per = 256 / G;
+    const int t = threadIdx.x, g = t % G, ph = t / G;
+    const int r0 = blockIdx.x * rows_per_block, r1 = min(M, r0 + rows_per_block);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    constexpr int U = 4;  // rows in flight per thread
+    if (ph < per)
+        for (int m0 = r0 + ph; m0 < r1; m0 += U * per) {
+            uint4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int m = m0 + u * per;
+                v[u] = m < r1 ? *reinterpret_cast<const uint4 *>(z + (size_t)m * N + g * 8)
+                              : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc[j] += bf2f((u16)(w[j >> 1] >> ((j & 1) * 16)));
+            }
+        }
+    __shared__ float part[256 * 8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part[t * 8 + j] = acc[j];
+    __syncthreads();
+    for (int c = t; c < N; c += 256) {
+        const int gc = c >> 3, j = c & 7;
+        float v = 0.f;
+        for (int q = 0; q < per; ++q) v += part[(q * G + gc) * 8 + j];
+        unsafeAtomicAdd(out + c, v);
+    }
+}
+
+// Column sums of a bf16 matrix [M][N] added into out[N] (bias gradients), any N.
 __global__ void __launch_bounds__(256) k_colsum(const u16 *__restrict__ z, int M, int N,
                                                 int rows_per_block, float *__restrict__ out)
 {
@@ -297,6 +379,20 @@ __global__ void __launch_bounds__(256) k_colsum(const u16 *__restrict__ z, int M
             part[threadIdx.x + 192];
         unsafeAtomicAdd(out + n, s);
     }
+}
+
+// Bias gradient: column sums of dz [M][N] added into db (the vector form where it applies).
+static hipError_t colsum(hipStream_t st, const u16 *dz, int M, int N, float *db)
+{
+    if (N % 8 == 0 && N <= 2048 && ((uintptr_t)dz & 15) == 0) {
+        const int rows = 2048;
+        k_colsum8<<<(M + rows - 1) / rows, 256, 0, st>>>(dz, M, N, rows, db);
+    } else {
+        const int rows = 4096;
+        dim3 grid((N + 63) / 64, (M + rows - 1) / rows);
+        k_colsum<<<grid, 256, 0, st>>>(dz, M, N, rows, db);
+    }
+    return hipGetLastError();
 }
 
 // float32 weights [R][T][C] -> bf16 copies in [R][T][C] and transposed [C][T][R] layouts.
@@ -455,17 +551,19 @@ int dbmp_cnn_conv_backward_weight(void *stream, const uint16_t *x, const uint16_
         Cout < 1)
         return DBMP_CNN_EINVAL;
     const int OH = H / 2, OW = W / 2, P = B * OH * OW, N = 9 * Cin;
-    LTrans la{dz, Cout, Cout, P};                 // A(oc, p) = dz[p][oc]
-    LIm2colT lb{x, H, W, Cin, OH, OW, N, P};      // B(n, p) = patch value
     EAdd ep{dw, N};
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = gemm(st, la, lb, ep, Cout, N, P, splits_for(Cout, N, P));
-    if (e == hipSuccess && db) {
-        const int rows = 4096;
-        dim3 grid((Cout + 63) / 64, (P + rows - 1) / rows);
-        k_colsum<<<grid, 256, 0, st>>>(dz, P, Cout, rows, db);
-        e = hipGetLastError();
-    }
+    const int sp = splits_for(Cout, N, P);
+    hipError_t e;
+    // A(oc, p) = dz[p][oc], B(n, p) = patch value: both read across K = output pixels, their
+    // rows (channels) contiguous in NHWC, so 16-byte loads where the channel counts allow
+    if (Cout % 8 == 0 && Cin % 8 == 0 && ((uintptr_t)dz & 15) == 0 && ((uintptr_t)x & 15) == 0)
+        e = gemm(st, LTrans<TVEC>{dz, Cout, Cout, P}, LIm2colT<TVEC>{x, H, W, Cin, OH, OW, N, P},
+                 ep, Cout, N, P, sp);
+    else
+        e = gemm(st, LTrans<SCAL>{dz, Cout, Cout, P}, LIm2colT<SCAL>{x, H, W, Cin, OH, OW, N, P},
+                 ep, Cout, N, P, sp);
+    if (e == hipSuccess && db) e = colsum(st, dz, P, Cout, db);
     return status(e);
 }
 
@@ -493,16 +591,16 @@ int dbmp_cnn_linear_backward_weight(void *stream, const uint16_t *x, const uint1
                                     int K, int N, float *dw, float *db)
 {
     if (!x || !dz || !dw || B < 1 || K < 1 || N < 1) return DBMP_CNN_EINVAL;
-    LTrans la{dz, N, N, B};  // A(n, b) = dz[b][n]
-    LTrans lb{x, K, K, B};   // B(k, b) = x[b][k]
     EAdd ep{dw, K};
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = gemm(st, la, lb, ep, N, K, B, splits_for(N, K, B));
-    if (e == hipSuccess && db) {
-        dim3 grid((N + 63) / 64, 1);
-        k_colsum<<<grid, 256, 0, st>>>(dz, B, N, B, db);
-        e = hipGetLastError();
-    }
+    const int sp = splits_for(N, K, B);
+    hipError_t e;
+    // A(n, b) = dz[b][n], B(k, b) = x[b][k]
+    if (N % 8 == 0 && K % 8 == 0 && ((uintptr_t)dz & 15) == 0 && ((uintptr_t)x & 15) == 0)
+        e = gemm(st, LTrans<TVEC>{dz, N, N, B}, LTrans<TVEC>{x, K, K, B}, ep, N, K, B, sp);
+    else
+        e = gemm(st, LTrans<SCAL>{dz, N, N, B}, LTrans<SCAL>{x, K, K, B}, ep, N, K, B, sp);
+    if (e == hipSuccess && db) e = colsum(st, dz, B, N, db);
     return status(e);
 }
 

@@ -61,17 +61,28 @@ k_mse_grad(const float4 *__restrict__ img, const float4 *__restrict__ tgt, long 
     }
 }
 
+constexpr int ADAM_PER_THREAD = 4;
+
 __global__ void __launch_bounds__(256)
 k_adam(float *__restrict__ p, float *__restrict__ g, float *__restrict__ m,
        float *__restrict__ v, long long n, float lr, float b1, float b2, float eps,
        int *__restrict__ step, unsigned int *__restrict__ done, int zero_grad)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int t = *step + 1;
-    if (i < n) {
-        // bias corrections 1 - beta^t, evaluated in float64
-        const float c1 = (float)(1.0 - pow((double)b1, (double)t));
-        const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+    // bias corrections 1 - beta^t, evaluated in float64 once per workgroup (a float64 pow costs
+    // a wave hundreds of instructions; per element it dominated the kernel)
+    __shared__ float s_c[2];
+    if (threadIdx.x == 0) {
+        s_c[0] = (float)(1.0 - pow((double)b1, (double)t));
+        s_c[1] = (float)(1.0 - pow((double)b2, (double)t));
+    }
+    __syncthreads();
+    const float c1 = s_c[0], c2 = s_c[1];
+    const long long base = (long long)blockIdx.x * (blockDim.x * ADAM_PER_THREAD);
+#pragma unroll
+    for (int u = 0; u < ADAM_PER_THREAD; ++u) {
+        const long long i = base + (long long)u * blockDim.x + threadIdx.x;
+        if (i >= n) break;
         const float gi = g[i];
         if (zero_grad) g[i] = 0.f;  // ready for the next accumulating backward
         const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
@@ -123,7 +134,8 @@ extern "C" int dbmp_adam_step(dbmp_stream stream, float *params, float *grad, fl
     if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
         return DBMP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    k_adam<<<(unsigned)(n > 0 ? (n + 255) / 256 : 1), 256, 0, st>>>(
+    const long long per_block = 256LL * ADAM_PER_THREAD;
+    k_adam<<<(unsigned)(n > 0 ? (n + per_block - 1) / per_block : 1), 256, 0, st>>>(
         params, grad, m, v, n, lr, beta1, beta2, eps, step, (unsigned int *)(step + 1),
         zero_grad);
     return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP;

@@ -187,6 +187,14 @@ __device__ __forceinline__ void blend(const Cell<TexT> &c, float &M, float &MU, 
     MU = fmaf(c.wv, d1 - d0, d0);
 }
 
+// Visits per wave whose bilinear values the fused step keeps for its backward (3 vector
+// registers each; 0 keeps none). Six keep the fused 16 x 16 kernel at 72 vector registers,
+// 7 waves per SIMD; at 2048^2 it took 175 us against 193 us with none and 184 us with four,
+// while eight (84 registers, 5 waves) took 196 us.
+#ifndef STORED_VISITS
+#define STORED_VISITS 6
+#endif
+
 // Lists up to this length are sorted in LDS, longer ones in place in global memory. At 512
 // entries for 8 x 8 and 16 x 16 tiles the buffer takes 2 KB; at 2,048 it limited the 16 x 16
 // forward to 7 workgroups per CU by LDS (lists at these workloads are far shorter).
@@ -328,14 +336,28 @@ __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__r
     }
 }
 
+// Visits whose per-lane bilinear values (M and its derivatives along U' and V') the fused
+// step's forward keeps in registers for its own backward: the first SV visits of a list that
+// fits one batch. The backward then neither repeats the support test nor fetches and blends the
+// texels of those visits; it only recomputes U', V' for the geometric terms. Lanes outside a
+// visit's support sampled the all-zero cell, so their stored values are exactly 0. SV = 1 with
+// n = 0 is the form that stores nothing.
+template <int SV>
+struct Stored {
+    float M[SV], MU[SV], MV[SV];
+    int e[SV];
+    int n = 0;     // visits stored
+    int last = -1; // the last stored visit's batch entry (visits go in ascending entry order)
+};
+
 // FUSED: the forward of a fit step, followed in the same workgroup by the backward of the MSE
 // loss against `target` (the image, the per-pixel (K, T_K) and, for a list of at most 64
 // entries, the staged records are still on chip); the gradient is added to dparams and the
 // tile's squared error written to loss_tile.
 // The backward's walk over a tile's sorted list (defined below, after the forward kernel that
 // also runs it in the fused fit step).
-template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, typename IdAt>
-__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
+template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, int SV, typename IdAt>
+__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged, const Stored<SV> &st,
                                          PrimRec *__restrict__ s_rec,
                                          float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
@@ -362,7 +384,9 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
     constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT, PIPE = LAUNCH == LAUNCH_TILE_PIPE;
-    // a fit step's gradient now awaits its Adam update (applied by the next binning)
+    // the fused step's one-cell build keeps its first visits' bilinear values for the backward
+    constexpr bool STORE = FUSED && LAUNCH == LAUNCH_TILE && STORED_VISITS > 0;
+    constexpr int SV = STORE ? STORED_VISITS : 1;
     // A fit step's Adam state {updates applied, unused, gradient pending, unused}: this step's
     // binning applied the pending update if one was marked (count it), and this launch leaves a
     // new gradient pending. One thread, after the binning has ended (stream order) and before
@@ -471,9 +495,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         // texels is the same on every path): outside the support alpha = 0, which leaves C and
         // T exactly as they were; only the record of K is confined to the support. The other
         // walk evaluates the same arithmetic on the support lanes only.
-        auto over = [&](int j, const PrimRec &r, const Cell<TexT> &c, uint64_t m) {
-            float M, MU, MV;
-            blend<TexT>(c, M, MU, MV);
+        auto over_m = [&](int j, const PrimRec &r, float M, uint64_t m) {
             const float a = r.ka * M;  // Eq. (3)
             if (__builtin_amdgcn_inverse_ballot_w64(m) && T >= DBMP_TAU) { K = j; TK = T; }
             const float w = T * a;
@@ -482,6 +504,12 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
             C2 = fmaf(w, r.cb, C2);
             T = T * (1.f - a);
         };
+        auto over = [&](int j, const PrimRec &r, const Cell<TexT> &c, uint64_t m) {
+            float M, MU, MV;
+            blend<TexT>(c, M, MU, MV);
+            over_m(j, r, M, m);
+        };
+        Stored<SV> st;
         auto composite = [&](auto id_at) {
             for (int b0 = 0; b0 < n; b0 += BATCH) {
                 const int cnt = min(BATCH, n - b0);
@@ -503,6 +531,34 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                         over(b0 + eb, s_rec[eb], cb, mb);
                     }
                 } else {
+                    if constexpr (STORE) {
+                        // a list of one batch: its first visits composite on every lane (the
+                        // all-zero cell outside the support) and keep M, M_U, M_V for the
+                        // backward of this workgroup
+                        if (n <= BATCH) {
+#pragma unroll
+                            for (int v = 0; v < SV; ++v) {
+                                double U, V;
+                                uint64_t m;
+                                const int e = find(hits, U, V, m);
+                                if (e < 0) break;
+                                const PrimRec &r = s_rec[e];
+                                Cell<TexT> c;
+                                request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V,
+                                                          __builtin_amdgcn_inverse_ballot_w64(m),
+                                                          zcell);
+                                float M, MU, MV;
+                                blend<TexT>(c, M, MU, MV);
+                                over_m(b0 + e, r, M, m);
+                                st.M[v] = M;
+                                st.MU[v] = MU;
+                                st.MV[v] = MV;
+                                st.e[v] = e;
+                                st.n = v + 1;
+                                st.last = e;
+                            }
+                        }
+                    }
                     while (hits) {  // ascending list order: front to back
                         const int e = __builtin_ctzll(hits);
                         hits &= hits - 1;
@@ -571,7 +627,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         const int lane = threadIdx.x & 63;
         const bool staged = n <= BATCH;  // the forward's only batch is still in s_rec
         if (in_lds)
-            bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return s_ids[j]; }, staged, s_rec,
+            bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return s_ids[j]; }, staged, st, s_rec,
                                             s_grad,
                                       recs,
                                       atlas, Wp, zcell, tg, vmask, g0, g1, g2, 0.f, b0, b1,
@@ -580,7 +636,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                       lane);
         else
             bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return ((volatile int *)seg)[j]; },
-                                      staged, s_rec, s_grad, recs, atlas, Wp, zcell, tg, vmask,
+                                      staged, Stored<1>(), s_rec, s_grad, recs, atlas, Wp, zcell, tg, vmask,
                                       g0,
                                       g1, g2,
                                       0.f, b0, b1, b2, tg.valid ? K : -1, TK, dparams, cu1, cv1,
@@ -620,8 +676,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 // conversion): summing the uncentred coordinates and subtracting cu1 s0 + cv1 s1 at the flush
 // instead saves two instructions but cancels, and it was measured to lose about two decimal
 // digits on the angle's gradient.
-template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, typename IdAt>
-__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
+template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, int SV, typename IdAt>
+__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged, const Stored<SV> &st,
                                          PrimRec *__restrict__ s_rec,
                                          float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
@@ -663,11 +719,9 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
     // every lane runs the update; outside the support alpha = M = dM = 0, so its partials are
     // zero and its state (T, G, B) passes through unchanged (no branch and no zeroing: the
     // vector instructions issue for the whole wave either way)
-    auto under = [&](int e, int j, const Cell<TexT> &c, float Ub, float Vb) {
+    auto under_m = [&](int e, int j, float M, float MU, float MV, float Ub, float Vb) {
         const PrimRec &r = s_rec[e];
         float d[8];
-        float M, MU, MV;
-        blend<TexT>(c, M, MU, MV);
         const float a = r.ka * M;
         const float m = 1.f - a;
         // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp; exactly 1
@@ -705,6 +759,11 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             __hip_atomic_fetch_add(s_grad + e * 8 + (lane >> 3), tot, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
     };
+    auto under = [&](int e, int j, const Cell<TexT> &c, float Ub, float Vb) {
+        float M, MU, MV;
+        blend<TexT>(c, M, MU, MV);
+        under_m(e, j, M, MU, MV, Ub, Vb);
+    };
     for (int hi = n; hi > 0; hi -= BATCH) {
         const int b0 = max(0, hi - BATCH), cnt = hi - b0;
         if (!(staged && b0 == 0)) {
@@ -713,6 +772,10 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             __syncthreads();
         }
         uint64_t hits = batch_hits(s_rec, cnt, tg.bx0, tg.by0);
+        // entries up to the last stored visit were either stored or had no support lane: the
+        // walk below takes the entries behind them, then the stored visits
+        const bool use_st = staged && b0 == 0 && st.n > 0;
+        if (use_st) hits &= st.last >= 63 ? 0ull : ~0ull << (st.last + 1);
         if constexpr (PIPE) {
             // two cells in turn: the next entry's texels are in flight while the current one's
             // gradient terms are formed (the last request of a batch is dropped)
@@ -739,6 +802,18 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                 request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V,
                                           __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
                 under(e, b0 + e, c, (float)(U - cu1), (float)(V - cv1));
+            }
+        }
+        if (use_st) {  // the stored visits, back to front
+#pragma unroll
+            for (int v = SV - 1; v >= 0; --v) {
+                if (v >= st.n) continue;
+                const int e = st.e[v];
+                const PrimRec &r = s_rec[e];
+                const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
+                const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
+                under_m(e, b0 + e, st.M[v], st.MU[v], st.MV[v], (float)(U - cu1),
+                        (float)(V - cv1));
             }
         }
         // every wave has added its partials: one global atomic per (entry, parameter) per tile
@@ -816,7 +891,8 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             TK = saveT[gp];
         }
         const int *seg = lists + (size_t)tile * list_cap;
-        bwd_walk<TS * TS, TexT, HAS_GA, PIPE>(n, [&](int j) { return seg[j]; }, false, s_rec,
+        bwd_walk<TS * TS, TexT, HAS_GA, PIPE>(n, [&](int j) { return seg[j]; }, false,
+                                              Stored<1>(), s_rec,
                                               s_grad,
                                         recs,
                                         atlas, Wp, zcell, tg, vmask, g0, g1, g2, ga, G0, G1, G2,
