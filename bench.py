@@ -232,6 +232,7 @@ def main():
         % (k_fused * 1e6, ppl, roofline["frac"]))
     extra = {
         "adam_iters_per_s_graph": round(args.steps / wall, 2),
+        "hw_times_n_per_s": round(H * W * N * args.steps / wall),  # dense-equivalent rate
         "state": "every timed step starts from the initial parameters with a pending gradient "
                  "(restored by a 2 MB device copy inside the graph, included in the time)",
         "pairs_per_step": round(pairs_timed / args.steps),
@@ -356,6 +357,7 @@ def main():
         out["cpu_baseline"] = {
             "value": round(sp / tc, 1), "unit": "primitive-pixel evals/s",
             "cores": oracle.threads(), "kind": "oracle",
+            "pair_tests_per_s": round(w * w * N / tc),
             "sample": "forward + backward of the central %dx%d window of the 2048x2048 workload "
                       "with all 65536 primitives (FP64, every primitive tested at every pixel; "
                       "pixels are independent, so the rate holds for the whole canvas): %d "

@@ -194,6 +194,13 @@ __device__ __forceinline__ void blend(const Cell<TexT> &c, float &M, float &MU, 
 #ifndef STORED_VISITS
 #define STORED_VISITS 6
 #endif
+// The same for the pipelined build, which runs where the grid itself holds at most 4 waves per
+// SIMD, so registers are not the limit there up to 128 (even number: the walk stores visits in
+// pairs). Ten keep the 16 x 16 build at 90 vector registers with no scalar-register spill
+// (twelve spill scalar registers).
+#ifndef STORED_VISITS_PIPE
+#define STORED_VISITS_PIPE 10
+#endif
 
 // Lists up to this length are sorted in LDS, longer ones in place in global memory. At 512
 // entries for 8 x 8 and 16 x 16 tiles the buffer takes 2 KB; at 2,048 it limited the 16 x 16
@@ -384,9 +391,12 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
     constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT, PIPE = LAUNCH == LAUNCH_TILE_PIPE;
-    // the fused step's one-cell build keeps its first visits' bilinear values for the backward
-    constexpr bool STORE = FUSED && LAUNCH == LAUNCH_TILE && STORED_VISITS > 0;
-    constexpr int SV = STORE ? STORED_VISITS : 1;
+    // the fused step keeps its first visits' bilinear values for the backward (the pipelined
+    // build runs where the grid leaves SIMDs with few waves, so registers are not its limit)
+    constexpr int SVN = LAUNCH == LAUNCH_TILE ? STORED_VISITS
+                        : LAUNCH == LAUNCH_TILE_PIPE ? STORED_VISITS_PIPE : 0;
+    constexpr bool STORE = FUSED && SVN > 0;
+    constexpr int SV = STORE ? SVN : 1;
     // A fit step's Adam state {updates applied, unused, gradient pending, unused}: this step's
     // binning applied the pending update if one was marked (count it), and this launch leaves a
     // new gradient pending. One thread, after the binning has ended (stream order) and before
@@ -523,6 +533,34 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                     Cell<TexT> ca, cb;
                     uint64_t ma, mb;
                     int ea = find_req(hits, ca, ma);
+                    if constexpr (STORE) {
+                        // a list of one batch: its first SV visits (the same pipelined walk,
+                        // unrolled two at a time) keep M, M_U, M_V for the backward
+                        static_assert(SV % 2 == 0, "stored visits go in pairs");
+                        if (n <= BATCH) {
+#pragma unroll
+                            for (int v = 0; v < SV; v += 2) {
+                                if (ea < 0) break;
+                                const int eb = find_req(hits, cb, mb);
+                                {
+                                    float M, MU, MV;
+                                    blend<TexT>(ca, M, MU, MV);
+                                    over_m(b0 + ea, s_rec[ea], M, ma);
+                                    st.M[v] = M; st.MU[v] = MU; st.MV[v] = MV;
+                                    st.e[v] = ea; st.n = v + 1; st.last = ea;
+                                }
+                                if (eb < 0) { drop_cell(cb); ea = -1; break; }
+                                ea = find_req(hits, ca, ma);
+                                {
+                                    float M, MU, MV;
+                                    blend<TexT>(cb, M, MU, MV);
+                                    over_m(b0 + eb, s_rec[eb], M, mb);
+                                    st.M[v + 1] = M; st.MU[v + 1] = MU; st.MV[v + 1] = MV;
+                                    st.e[v + 1] = eb; st.n = v + 2; st.last = eb;
+                                }
+                            }
+                        }
+                    }
                     while (ea >= 0) {
                         const int eb = find_req(hits, cb, mb);
                         over(b0 + ea, s_rec[ea], ca, ma);

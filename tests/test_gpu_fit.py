@@ -568,6 +568,53 @@ def test_benchmark_fit_step_matches_oracle():
     f.check()
 
 
+@pytest.mark.parametrize("grow", [0.0, 0.7])
+def test_benchmark_2048_fit_step_matches_oracle_on_windows(grow):
+    """The benchmark's timed kernel in its own configuration (2048x2048, 65,536 primitives, bf16
+    atlas, 16x16 tiles in grid order, dbmp_fit_step from a captured graph: the binning, then the
+    fused forward + MSE backward in the one-cell walk build with stored visits), against the
+    FP64 oracle. The MSE runs over the whole canvas (scale 2 / (3 H W)), but the target equals
+    the library's own forward image outside two windows, so dL/dI vanishes exactly there (the
+    fused kernel composites the same image bit for bit): the gradient is that of the windows'
+    squared error, which the oracle evaluates pixel by pixel over the windows with every
+    primitive. Image on the windows within 1e-5, gradient within 1e-4 per block. grow > 0
+    enlarges every primitive (log s + grow): about twice the visits per wave, so most of them
+    run past the stored ones."""
+    from paper_2602_22625_amd.fit import Fitter
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c2")
+    H = W = 2048
+    params = d["params"].copy()
+    params[:, 2] += grow
+    p = torch.tensor(params, device="cuda")
+    idx = torch.tensor(d["idx"], device="cuda")
+    a = torch.tensor(d["atlas_bf16"].view(np.int16), device="cuda").view(torch.bfloat16)
+    full_target = torch.tensor(d["target"], device="cuda")
+    img0, _ = Renderer().render(p, idx, a, H, W, with_alpha=False)
+    target = img0.clone()
+    windows = [(1000, 1000, 48, 48), (96, 1900, 40, 48)]
+    for x0, y0, w, h in windows:
+        target[:, y0:y0 + h, x0:x0 + w] = full_target[:, y0:y0 + h, x0:x0 + w]
+    f = Fitter(p, idx, a, target.contiguous(), tile=16, lr=1e-2)
+    f.set_launch(16, capi.DBMP_SCHED_GRID)
+    f.capture(1)
+    assert f.adam_in_binning
+    f.step()
+    f.check()
+    img = f.image.cpu().numpy().astype(np.float64)
+    assert np.array_equal(f.image.cpu().numpy(), img0.cpu().numpy())
+    g_ref = np.zeros((params.shape[0], 8))
+    scale = 2.0 / (3.0 * H * W)
+    for x0, y0, w, h in windows:
+        crop = (x0, y0, w, h)
+        ref, _ = oracle.render(params, d["idx"], d["atlas"], H, W, crop=crop)
+        win = img[:, y0:y0 + h, x0:x0 + w]
+        assert np.max(np.abs(win - ref)) / np.max(np.abs(ref)) <= 1e-5
+        gI = scale * (ref - d["target"][:, y0:y0 + h, x0:x0 + w].astype(np.float64))
+        g_ref += oracle.render_backward(params, d["idx"], d["atlas"], H, W, gI, crop=crop)
+    _assert_grads_vs_oracle(f.grad.cpu().numpy(), g_ref)
+
+
 def test_fit_100_steps_final_psnr_matches_float64_oracle_fit():
     """The 128x128 workload's protocol: 100 plain Adam steps (lr 1e-2) through the timed path
     (graph-replayed dbmp_fit_step), against the same 100 steps of the FP64 oracle. Adam
