@@ -81,9 +81,9 @@ def decode(codes):
 
 # ------------------------------------------------------------------------------------------
 # Matrix-core work per image, as the layer kernels execute it (for the roofline): each layer is
-# one implicit GEMM of 2 M N K FLOP; the first layer's input carries 8 channels (3 used), and
-# the input gradient of a stride-2 convolution runs over every input pixel and all 9 taps (a
-# tap that does not reach the pixel contributes zeros).
+# one implicit GEMM of 2 M N K FLOP, and the input gradient of a stride-2 convolution one per
+# parity class of input pixels, over the 1, 2, 2 or 4 taps that reach that class; the first
+# layer's input carries 8 channels (3 used).
 # ------------------------------------------------------------------------------------------
 def _layer_gemms():
     """[(kind, M, N, K)] per image for the forward, input-gradient and weight-gradient GEMMs."""
@@ -94,7 +94,8 @@ def _layer_gemms():
         fwd.append((o * o, co, 9 * ci))
         bwd.append((co, 9 * ci, o * o))          # weight gradient
         if l > 0:
-            bwd.append((s * s, ci, 9 * co))      # input gradient
+            for taps in (1, 2, 2, 4):            # input gradient, per parity class
+                bwd.append((o * o, ci, taps * co))
         s = o
     fwd += [(POS, HIDDEN, FEAT), (POS, POS_OUT, HIDDEN)]
     bwd += [(POS_OUT, HIDDEN, POS), (POS, HIDDEN, POS_OUT),   # output layer: weight, input

@@ -6,8 +6,9 @@
 // kernel whose operands are produced by gather functors:
 //   convolution forward      M = output pixels (b, oy, ox), N = out channels, K = (ky, kx, ic):
 //                            A = the image patch under the filter (implicit im2col), B = W;
-//   convolution grad-input   M = input pixels (b, y, x), N = in channels, K = (ky, kx, oc):
-//                            A = output gradients that reach (y, x) through tap (ky, kx),
+//   convolution grad-input   one product per parity class of input pixels (y % 2, x % 2):
+//                            M = the class's pixels, N = in channels, K = (its taps, oc):
+//                            A = output gradients that reach (y, x) through those taps,
 //                            B = W with (ic) and (oc) swapped (a transposed copy);
 //   convolution grad-weight  M = out channels, N = (ky, kx, ic), K = output pixels:
 //                            A = output gradients, B = image patches (both read across K);
@@ -38,13 +39,14 @@ __device__ __forceinline__ u16 f2bf(float f)
 __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------------------------------------
-// Tiled product: 64 x 64 output tile per 256-thread workgroup, K in steps of 32. Each wave
-// computes a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16 (one 16x16x32 MFMA per tile and
-// K step). Operand tiles are staged in LDS with K contiguous (row pitch 40 bf16), so every
-// lane's 8-element MFMA operand is one 16-byte LDS read. Global loads for the next K step are
-// issued before the MFMAs of the current one.
+// Tiled product: 64 x 64 output tile per 256-thread workgroup, K in steps of 64. Each wave
+// computes a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16 (two 16x16x32 MFMAs per tile and
+// K step). Operand tiles are staged in LDS with K contiguous (row pitch 72 bf16), so every
+// lane's 8-element MFMA operand is one 16-byte LDS read. Every thread loads KS = 2 chunks of
+// 8 elements per operand and step (one per 32-wide half of the step); the loads for the next
+// step are issued before the MFMAs of the current one.
 // ------------------------------------------------------------------------------------------
-constexpr int BM = 64, BN = 64, BK = 32, NT = 256, LDK = BK + 8;
+constexpr int BM = 64, BN = 64, BK = 64, KS = BK / 32, NT = 256, LDK = BK + 8;
 
 // Operand loaders, by how their elements lie in memory:
 //   VEC   elements (row, k .. k+7) are contiguous: one 16-byte load (thread t loads row t/4,
@@ -106,25 +108,6 @@ struct LIm2col {  // row = output pixel (b, oy, ox), k = (ky, kx, ic); x NHWC [B
     }
 };
 
-struct LCol2im {  // row = input pixel (b, y, x), k = (ky, kx, oc); dz NHWC [B][OH][OW][Co]
-    static constexpr int KIND = VEC;
-    const u16 *dz;
-    int H, W, Co, OH, OW, M, K;
-    __device__ uint4 load8(int m, int k) const
-    {
-        if (m >= M || k >= K) return make_uint4(0, 0, 0, 0);
-        const int tap = k / Co, oc = k - tap * Co;
-        const int ky = tap / 3, kx = tap - 3 * ky;
-        const int b = m / (H * W), r = m - b * H * W;
-        const int y = r / W, x = r - y * W;
-        const int ty = y + 1 - ky, tx = x + 1 - kx;  // = 2 oy, 2 ox when the tap reaches (y, x)
-        if (ty < 0 || tx < 0 || (ty & 1) || (tx & 1)) return make_uint4(0, 0, 0, 0);
-        const int oy = ty >> 1, ox = tx >> 1;
-        if (oy >= OH || ox >= OW) return make_uint4(0, 0, 0, 0);
-        return *reinterpret_cast<const uint4 *>(dz + (((size_t)b * OH + oy) * OW + ox) * Co + oc);
-    }
-};
-
 template <int KD>
 struct LIm2colT {  // row = (ky, kx, ic), k = output pixel (b, oy, ox); x NHWC [B][H][W][C]
     static constexpr int KIND = KD;  // TVEC needs C % 8 == 0 (8 rows share one tap)
@@ -171,6 +154,73 @@ struct EAct {  // out = act(acc + bias[n]) as bf16 (and optionally float32), row
     }
 };
 
+// The input gradient of a stride-2 convolution, one parity class of input pixels at a time: a
+// pixel (y, x) with y % 2 == py, x % 2 == px is reached only by the taps with ky = (y + 1) % 2
+// (mod 2) and kx likewise (1 tap, 2 or 4: ky = ky0 + 2 i, i < nky), so each class is a product
+// over those taps alone, a quarter of the work of running all 9 taps over every pixel.
+struct Phase {
+    int py, px;     // the class's pixel parities
+    int ky0, nky;   // its taps along y: ky0, ky0 + 2, ... (nky of them)
+    int kx0, nkx;
+};
+// class z = 2 py + px: y even is reached by ky = 1 alone, y odd by ky = 0 and 2 (likewise x)
+__device__ __forceinline__ Phase phase_of(int z)
+{
+    const int py = z >> 1, px = z & 1;
+    return Phase{py, px, py ? 0 : 1, py ? 2 : 1, px ? 0 : 1, px ? 2 : 1};
+}
+
+struct LCol2imPhase {  // row = pixel (b, hy, hx) of the class, k = (tap, oc); dz NHWC
+    static constexpr int KIND = VEC;
+    const u16 *dz;
+    int H, W, Co, OH, OW, M, K;
+    Phase ph;
+    __device__ uint4 load8(int m, int k) const
+    {
+        if (m >= M || k >= K) return make_uint4(0, 0, 0, 0);
+        const int t = k / Co, oc = k - t * Co;
+        const int ty = t / ph.nkx, tx = t - ty * ph.nkx;
+        const int ky = ph.ky0 + 2 * ty, kx = ph.kx0 + 2 * tx;
+        const int W2 = W >> 1, HW4 = (H >> 1) * W2;
+        const int b = m / HW4, r = m - b * HW4, hy = r / W2, hx = r - hy * W2;
+        const int ty2 = 2 * hy + ph.py + 1 - ky, tx2 = 2 * hx + ph.px + 1 - kx;  // = 2 oy, 2 ox
+        if (ty2 < 0 || tx2 < 0) return make_uint4(0, 0, 0, 0);
+        const int oy = ty2 >> 1, ox = tx2 >> 1;
+        if (oy >= OH || ox >= OW) return make_uint4(0, 0, 0, 0);
+        return *reinterpret_cast<const uint4 *>(dz + (((size_t)b * OH + oy) * OW + ox) * Co + oc);
+    }
+};
+
+struct LTapW {  // row = ic, k = (tap of the class, oc); wt [Cin][3][3][Cout]
+    static constexpr int KIND = VEC;
+    const u16 *w;
+    int R, Co, K;
+    Phase ph;
+    __device__ uint4 load8(int row, int k) const
+    {
+        if (row >= R || k >= K) return make_uint4(0, 0, 0, 0);
+        const int t = k / Co, oc = k - t * Co;
+        const int ty = t / ph.nkx, tx = t - ty * ph.nkx;
+        const int ky = ph.ky0 + 2 * ty, kx = ph.kx0 + 2 * tx;
+        return *reinterpret_cast<const uint4 *>(w + ((size_t)(row * 3 + ky) * 3 + kx) * Co + oc);
+    }
+};
+
+struct EMaskPhase {  // EMask for row m of a parity class: the pixel it stands for
+    const u16 *mask;
+    u16 *out;
+    int C, H, W;
+    Phase ph;
+    __device__ void operator()(int m, int n, float v) const
+    {
+        const int W2 = W >> 1, HW4 = (H >> 1) * W2;
+        const int b = m / HW4, r = m - b * HW4, hy = r / W2, hx = r - hy * W2;
+        const size_t i = (((size_t)b * H + 2 * hy + ph.py) * W + 2 * hx + ph.px) * C + n;
+        if (mask && !(bf2f(mask[i]) > 0.f)) v = 0.f;
+        out[i] = f2bf(v);
+    }
+};
+
 struct EMask {  // out = acc * [mask > 0] as bf16: the gradient through the producing ReLU
     const u16 *mask;
     u16 *out;
@@ -181,6 +231,17 @@ struct EMask {  // out = acc * [mask > 0] as bf16: the gradient through the prod
         if (mask && !(bf2f(mask[i]) > 0.f)) v = 0.f;
         out[i] = f2bf(v);
     }
+};
+
+// The four parity classes run as one launch (gridDim.z = 4, no split of K): a workgroup takes
+// its class from blockIdx.z and sets its operands' taps and K from it.
+template <class L>
+struct is_phased {
+    static constexpr bool value = false;
+};
+template <>
+struct is_phased<LCol2imPhase> {
+    static constexpr bool value = true;
 };
 
 struct EAdd {  // out += acc (float atomics: split-K partial sums)
@@ -212,12 +273,12 @@ __device__ __forceinline__ void fetch(const L &l, int row0, int k0, uint4 &v)
 }
 
 template <class L>
-__device__ __forceinline__ void stash(u16 *s, const uint4 &v)
+__device__ __forceinline__ void stash(u16 *s, const uint4 &v, int koff)
 {
     int row, kc;
     if constexpr (L::KIND == TVEC) {  // 8 rows at one k: transposed into the K-contiguous tile
         row = (threadIdx.x & 7) * 8;
-        kc = threadIdx.x >> 3;
+        kc = koff + (int)(threadIdx.x >> 3);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 8; ++j)
@@ -231,7 +292,7 @@ __device__ __forceinline__ void stash(u16 *s, const uint4 &v)
         row = threadIdx.x & 63;
         kc = (threadIdx.x >> 6) * 8;
     }
-    *reinterpret_cast<uint4 *>(s + row * LDK + kc) = v;
+    *reinterpret_cast<uint4 *>(s + row * LDK + koff + kc) = v;
 }
 
 // gridDim = (ceil(M / 64), ceil(N / 64), splits): the long dimension (output pixels) on x;
@@ -242,8 +303,17 @@ __global__ void __launch_bounds__(NT) k_gemm(LA la, LB lb, EP ep, int M, int N, 
     __shared__ __attribute__((aligned(16))) u16 sA[BM * LDK];
     __shared__ __attribute__((aligned(16))) u16 sB[BN * LDK];
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int kbeg = blockIdx.z * kper;
-    const int kend = min(K, kbeg + kper);
+    int kbeg = blockIdx.z * kper;
+    int kend = min(K, kbeg + kper);
+    if constexpr (is_phased<LA>::value) {
+        const Phase ph = phase_of(blockIdx.z);
+        la.ph = ph;
+        lb.ph = ph;
+        ep.ph = ph;
+        la.K = lb.K = ph.nky * ph.nkx * la.Co;
+        kbeg = 0;
+        kend = la.K;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int r = lane & 15, kb = (lane >> 4) * 8;
@@ -252,32 +322,47 @@ __global__ void __launch_bounds__(NT) k_gemm(LA la, LB lb, EP ep, int M, int N, 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    uint4 va, vb;
+    uint4 va[KS], vb[KS];
     if (kbeg < kend) {
-        fetch(la, m0, kbeg, va);
-        fetch(lb, n0, kbeg, vb);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            fetch(la, m0, kbeg + 32 * s, va[s]);
+            fetch(lb, n0, kbeg + 32 * s, vb[s]);
+        }
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         __syncthreads();  // the previous step's LDS reads are done
-        stash<LA>(sA, va);
-        stash<LB>(sB, vb);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            stash<LA>(sA, va[s], 32 * s);
+            stash<LB>(sB, vb[s], 32 * s);
+        }
         __syncthreads();
         if (k0 + BK < kend) {  // next step's operands, in flight during the MFMAs
-            fetch(la, m0, k0 + BK, va);
-            fetch(lb, n0, k0 + BK, vb);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                fetch(la, m0, k0 + BK + 32 * s, va[s]);
+                fetch(lb, n0, k0 + BK + 32 * s, vb[s]);
+            }
         }
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            a[i] = *reinterpret_cast<const bf16x8 *>(sA + (wm * 32 + i * 16 + r) * LDK + kb);
+        for (int s = 0; s < KS; ++s) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            b[j] = *reinterpret_cast<const bf16x8 *>(sB + (wn * 32 + j * 16 + r) * LDK + kb);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8 *>(sA + (wm * 32 + i * 16 + r) * LDK +
+                                                         32 * s + kb);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *reinterpret_cast<const bf16x8 *>(sB + (wn * 32 + j * 16 + r) * LDK +
+                                                         32 * s + kb);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
     }
     // acc[i][j][e] holds C[row][col] with row = (lane / 16) * 4 + e, col = lane % 16 of the
     // 16 x 16 tile (i, j) of this wave's quarter.
@@ -313,7 +398,7 @@ static int splits_for(int M, int N, int K)
     const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
     const long long want = std::max(1LL, 1024 / std::max(1LL, tiles));
     const long long ksteps = (K + BK - 1) / BK;
-    return (int)std::min(want, std::max(1LL, ksteps / 8));
+    return (int)std::min(want, std::max(1LL, ksteps / 4));  // >= 256 of K per split
 }
 
 // ------------------------------------------------------------------------------------------
@@ -537,11 +622,16 @@ int dbmp_cnn_conv_backward_data(void *stream, const uint16_t *dz, int B, int H, 
     if (!dz || !wt || !dx || B < 1 || H < 2 || W < 2 || (H & 1) || (W & 1) || Cin < 1 ||
         Cout < 8 || (Cout & 7) || (Cin & 7))
         return DBMP_CNN_EINVAL;
-    const int OH = H / 2, OW = W / 2, M = B * H * W, K = 9 * Cout;
-    LCol2im la{dz, H, W, Cout, OH, OW, M, K};
-    LPlain lb{wt, K, Cin, K};  // wt [Cin][3][3][Cout]
-    EMask ep{mask, dx, Cin};
-    return status(gemm((hipStream_t)stream, la, lb, ep, M, Cin, K, 1));
+    const int OH = H / 2, OW = W / 2, M4 = B * OH * OW;
+    // one launch over the four parity classes (the kernel sets each class's taps and K)
+    const Phase none{0, 0, 0, 0, 0, 0};
+    LCol2imPhase la{dz, H, W, Cout, OH, OW, M4, 0, none};
+    LTapW lb{wt, Cin, Cout, 0, none};
+    EMaskPhase ep{mask, dx, Cin, H, W, none};
+    dim3 grid((M4 + BM - 1) / BM, (Cin + BN - 1) / BN, 4);
+    k_gemm<LCol2imPhase, LTapW, EMaskPhase><<<grid, NT, 0, (hipStream_t)stream>>>(la, lb, ep, M4,
+                                                                                 Cin, 0, 0);
+    return status(hipGetLastError());
 }
 
 int dbmp_cnn_conv_backward_weight(void *stream, const uint16_t *x, const uint16_t *dz, int B,
