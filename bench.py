@@ -176,6 +176,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-f16", action="store_true")
     ap.add_argument("--c4-pairs", type=int, default=10000)
     ap.add_argument("--c4-epochs", type=int, default=20)
     ap.add_argument("--cpu-window", type=int, default=192)
@@ -310,6 +311,11 @@ def main():
     log("c2 separate: fwd %.3f ms bwd %.3f ms" % (f2 * 1e3, b2 * 1e3))
     del fit, R2
 
+    # ---------------- the reduced-precision raster (fp16 texels) on the same workload ----------
+    if not args.no_f16:
+        extra["f16_raster_2048sq"] = bench_f16(args, capi, metrics, Fitter, wl, d, p0, idx,
+                                               target, k_fused, extra, np, torch, dev)
+
     # ---------------- 512x512 / 4,096 primitives (the previous headline workload) --------------
     if not args.no_c1:
         wl1, d1, q0, idx1, atl1, tgt1 = load_workload("c1", synth, np, torch, dev)
@@ -364,6 +370,35 @@ def main():
                       "evaluated pairs in %.2f s" % (w, w, sp, tc)}
         log("cpu baseline %.3e evals/s on %d threads" % (sp / tc, oracle.threads()))
     print(json.dumps(out), flush=True)
+
+
+def bench_f16(args, capi, metrics, Fitter, wl, d, p0, idx, target, k_bf16, extra, np, torch,
+              dev):
+    """The headline fit step with the atlas in fp16 (the reduced-precision raster: packed fp16
+    texel pairs and blend, float32 compositing and gradients): the same held-state timing, the
+    fused kernel's duration beside the bf16 build's, and the fit after 100 steps beside the
+    bf16 fit's PSNR. The bitmaps are the bf16 values, which fp16 holds exactly above 2^-14."""
+    H, W, N = wl.H, wl.W, wl.N
+    a16 = torch.tensor(d["atlas"].astype(np.float16), device=dev)
+    fit, _ = held_fit(Fitter, capi, wl, p0, idx, a16, target, capi.DBMP_SCHED_GRID, 10)
+    wall, pairs = time_steps(fit, capi, torch, 100, 10, 10)
+    k16, ppl = fused_kernel_time(fit, capi, np, torch, 100)
+    del fit
+    fit100, _ = held_fit(Fitter, capi, wl, p0, idx, a16, target, capi.DBMP_SCHED_GRID, 10,
+                         pre_steps=100)
+    w100, p100 = time_steps(fit100, capi, torch, 50, 10, 10)
+    psnr100 = fit100.psnr()
+    del fit100
+    rf = roofline_block("k_raster_fwd<16, _Float16, false, true, 0>", ppl, k16, metrics,
+                        metrics.fused_algorithmic_bytes(H, W, N, a16.numel() * 2), None)
+    log("f16 raster: %.4f ms/step, fused %.1f us (bf16 %.1f us), psnr@100 %.3f"
+        % (1e3 * wall / 100, k16 * 1e6, k_bf16 * 1e6, psnr100))
+    return {"ms_per_step": round(1e3 * wall / 100, 5), "evals_per_s": round(pairs / wall),
+            "fused_kernel_us": round(k16 * 1e6, 2), "bf16_fused_kernel_us": round(k_bf16 * 1e6, 2),
+            "fused_speedup_vs_bf16": round(k_bf16 / k16, 4), "roofline_frac": rf["frac"],
+            "after_100_steps": {"ms_per_step": round(1e3 * w100 / 50, 5),
+                                "evals_per_s": round(p100 / w100), "psnr": round(psnr100, 3),
+                                "bf16_psnr": extra.get("c2_after_100_steps", {}).get("psnr")}}
 
 
 def bench_c3(args, synth, capi, autotune, BatchFitter, Fitter, np, torch, dev):

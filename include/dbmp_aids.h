@@ -26,8 +26,8 @@ typedef void *dbmp_aids_stream; /* hipStream_t */
  * convolved with a Gaussian of standard deviation `sigma` texels, taps d = -r..r with
  * r = floor(truncate * sigma + 0.5) (truncate = 3 is the usual cut), normalised to sum 1;
  * texels outside the bitmap read 0 and the bitmap keeps its size. Separable, float32.
- *   atlas  device [B, Hb, Wb], DBMP_F32 or DBMP_BF16 (diffbmp.h); out: same layout and dtype,
- *          must not overlap atlas (bf16 results rounded to nearest even).
+ *   atlas  device [B, Hb, Wb], DBMP_F32, DBMP_BF16 or DBMP_F16 (diffbmp.h); out: same layout
+ *          and dtype, must not overlap atlas (bf16 and f16 results rounded to nearest even).
  * sigma in (0, 8], r <= 16, Wb <= 1024.
  */
 int dbmp_blur_atlas(dbmp_aids_stream stream, const void *atlas, int B, int Hb, int Wb,

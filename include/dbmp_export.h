@@ -12,7 +12,7 @@
  * The export canvas is round(rho H) x round(rho W).
  *
  * Conventions as in diffbmp.h (device pointers owned by the caller, parameter rows [N, 8],
- * atlas [B, Hb, Wb] float32 or bfloat16). Calls only enqueue work on `stream`.
+ * atlas [B, Hb, Wb] float32, bfloat16 or float16). Calls only enqueue work on `stream`.
  */
 #ifndef DBMP_EXPORT_H
 #define DBMP_EXPORT_H

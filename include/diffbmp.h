@@ -18,8 +18,13 @@
  *     x, y in pixels with pixel (px, py) at canvas point (px, py) (origin top-left, y down);
  *     s = exp(log_s) is the half-extent in pixels (Eq. 1 divides by s); theta in radians.
  *   - atlas_idx: device int32 [N], the bitmap of each primitive, in [0, B).
- *   - atlas: device [B, Hb, Wb] row-major, float32 or bfloat16 (DBMP_F32 / DBMP_BF16), values
- *     are template masks, normally in [0, 1]; Hb, Wb >= 2. Texels outside a bitmap read as 0.
+ *   - atlas: device [B, Hb, Wb] row-major, float32, bfloat16 or float16 (DBMP_F32, DBMP_BF16,
+ *     DBMP_F16), values are template masks, normally in [0, 1]; Hb, Wb >= 2. Texels outside a
+ *     bitmap read as 0. A float32 or bfloat16 atlas is sampled in float32. A float16 atlas
+ *     selects the reduced-precision raster (the half-precision path of Sec. 3.1.2): each cell's
+ *     texel pairs are fetched and bilinearly blended in packed fp16 (the blend's M, dM/dU' and
+ *     dM/dV' carry fp16 rounding, about 3e-3 absolute for texels in [0, 1]); compositing,
+ *     gradients and every accumulation stay in float32.
  *   - images are planar float32 [3, H, W]; alpha maps float32 [H, W].
  *   - every device pointer is owned by the caller and must stay valid (and unchanged) until the
  *     work queued on `stream` has finished; the library never frees caller memory.
@@ -54,7 +59,7 @@ typedef enum {
     DBMP_ENONFINITE = -6  /* a parameter or atlas texel is NaN or infinite */
 } dbmp_status;
 
-typedef enum { DBMP_F32 = 0, DBMP_BF16 = 1 } dbmp_dtype;
+typedef enum { DBMP_F32 = 0, DBMP_BF16 = 1, DBMP_F16 = 2 } dbmp_dtype;
 
 /* Creates a context on HIP device `device`. The context owns the workspace (per-primitive
  * records, the per-tile primitive lists, the padded atlas and the per-pixel state the backward

@@ -17,6 +17,12 @@ HEADER_EXPORT = os.path.join(os.path.dirname(capi.HERE), "include", "dbmp_export
 _lib = None
 
 
+def _atlas_code(a):
+    import torch
+    return {torch.bfloat16: capi.DBMP_BF16, torch.float16: capi.DBMP_F16}.get(a.dtype,
+                                                                              capi.DBMP_F32)
+
+
 def load():
     global _lib
     if _lib is not None:
@@ -109,11 +115,12 @@ def dbmp_export_layers(stream, params, atlas_idx, N, atlas, B, Hb, Wb, atlas_dty
 # Helpers: outputs allocated with PyTorch, random inputs drawn on the device
 # ------------------------------------------------------------------------------------------
 def blur_atlas(atlas, sigma=1.0, truncate=3.0):
-    """Blurred copy of a [B, Hb, Wb] float32 or bfloat16 device atlas (soft rasterisation)."""
+    """Blurred copy of a [B, Hb, Wb] float32, bfloat16 or float16 device atlas (soft
+    rasterisation)."""
     import torch
     a = atlas if atlas.dim() == 3 else atlas[None]
     a = a.contiguous()
-    code = capi.DBMP_BF16 if a.dtype == torch.bfloat16 else capi.DBMP_F32
+    code = _atlas_code(a)
     out = torch.empty_like(a)
     dbmp_blur_atlas(capi.stream_handle(), a, a.shape[0], a.shape[1], a.shape[2], code, sigma,
                     truncate, out)
@@ -149,7 +156,7 @@ def export_layers(params, atlas_idx, atlas, H, W, rho=2.0, alpha_max=1.0):
     import torch
     dev = params.device
     a = atlas if atlas.dim() == 3 else atlas[None]
-    code = capi.DBMP_BF16 if a.dtype == torch.bfloat16 else capi.DBMP_F32
+    code = _atlas_code(a)
     N = params.shape[0]
     B, Hb, Wb = a.shape
     boxes = torch.empty(max(N, 1), 4, dtype=torch.int32, device=dev)

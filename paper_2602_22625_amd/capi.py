@@ -14,7 +14,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "diffbmp.h")
 
 DBMP_OK, DBMP_EINVAL, DBMP_ENOMEM, DBMP_EHIP, DBMP_EOVERFLOW, DBMP_ESTATE, DBMP_ENONFINITE = \
     0, -1, -2, -3, -4, -5, -6
-DBMP_F32, DBMP_BF16 = 0, 1
+DBMP_F32, DBMP_BF16, DBMP_F16 = 0, 1, 2
 DBMP_SCHED_GRID, DBMP_SCHED_SORTED, DBMP_SCHED_PERSISTENT = 0, 1, 2
 DBMP_NOALLOC_SCRATCH_MB = 64  # include/diffbmp.h
 STATUS_NAMES = {0: "DBMP_OK", -1: "DBMP_EINVAL", -2: "DBMP_ENOMEM", -3: "DBMP_EHIP",

@@ -35,6 +35,10 @@ template <> __device__ __forceinline__ uint16_t from_f32<uint16_t>(float v)
     u += 0x7fffu + ((u >> 16) & 1u);                                // round to nearest even
     return (uint16_t)(u >> 16);
 }
+template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v)
+{
+    return (_Float16)v;  // round to nearest even
+}
 
 template <typename TexT>
 __global__ void __launch_bounds__(256)
@@ -361,7 +365,8 @@ int dbmp_blur_atlas(dbmp_aids_stream stream, const void *atlas, int B, int Hb, i
                     int atlas_dtype, float sigma, float truncate, void *out)
 {
     if (!atlas || !out || B < 1 || Hb < 1 || Wb < 1 || Wb > 1024) return DBMP_EINVAL;
-    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16) return DBMP_EINVAL;
+    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16 && atlas_dtype != DBMP_F16)
+        return DBMP_EINVAL;
     if (!(sigma > 0.f && sigma <= 8.f) || !(truncate > 0.f)) return DBMP_EINVAL;
     const int r = (int)(truncate * (double)sigma + 0.5);
     if (r > BLUR_RMAX) return DBMP_EINVAL;
@@ -382,6 +387,9 @@ int dbmp_blur_atlas(dbmp_aids_stream stream, const void *atlas, int B, int Hb, i
     hipStream_t st = (hipStream_t)stream;
     if (atlas_dtype == DBMP_F32)
         k_blur<float><<<grid, 256, lds, st>>>((const float *)atlas, (float *)out, Hb, Wb, band, t);
+    else if (atlas_dtype == DBMP_F16)
+        k_blur<_Float16><<<grid, 256, lds, st>>>((const _Float16 *)atlas, (_Float16 *)out, Hb, Wb,
+                                                  band, t);
     else
         k_blur<uint16_t><<<grid, 256, lds, st>>>((const uint16_t *)atlas, (uint16_t *)out, Hb, Wb,
                                                   band, t);

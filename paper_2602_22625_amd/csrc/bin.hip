@@ -560,6 +560,10 @@ hipError_t launch_binning(const BinArgs &a, hipStream_t st)
         if (a.dtype == 0)
             k_setup<float><<<a.B, SETUP_THREADS, 0, st>>>((const float *)a.atlas, a.B, a.Hb, a.Wb,
                                                            (float *)a.atlas_pad, a.Wp, a.box);
+        else if (a.dtype == 2)
+            k_setup<_Float16><<<a.B, SETUP_THREADS, 0, st>>>((const _Float16 *)a.atlas, a.B, a.Hb,
+                                                              a.Wb, (_Float16 *)a.atlas_pad, a.Wp,
+                                                              a.box);
         else
             k_setup<uint16_t><<<a.B, SETUP_THREADS, 0, st>>>((const uint16_t *)a.atlas, a.B, a.Hb,
                                                               a.Wb, (uint16_t *)a.atlas_pad, a.Wp,

@@ -143,7 +143,8 @@ int set_atlas_impl(dbmp_ctx *c, hipStream_t st, const void *atlas, int B, int Hb
                    int dtype)
 {
     if (!atlas || B < 1 || Hb < 2 || Wb < 2) return fail(c, DBMP_EINVAL, "bad atlas shape");
-    if (dtype != DBMP_F32 && dtype != DBMP_BF16) return fail(c, DBMP_EINVAL, "bad atlas dtype");
+    if (dtype != DBMP_F32 && dtype != DBMP_BF16 && dtype != DBMP_F16)
+        return fail(c, DBMP_EINVAL, "bad atlas dtype");
     const int Hp = Hb + 2, Wp = Wb + 2;
     const size_t esz = dtype == DBMP_F32 ? 4 : 2;
     if (!atlas_addressable(B, Hb, Wb, (long long)esz))

@@ -94,6 +94,7 @@ template <> __device__ __forceinline__ float texel<uint16_t>(uint16_t v)
 {
     return __uint_as_float(((uint32_t)v) << 16);  // bf16 -> f32 widening is exact
 }
+template <> __device__ __forceinline__ float texel<_Float16>(_Float16 v) { return (float)v; }
 
 // Launch arguments shared by the host code and the launchers.
 // Adam applied by the binning to a gradient left pending by the previous fit step (see
@@ -112,7 +113,7 @@ struct BinArgs {
     int n_images;
     int n_tiles;
     const void *atlas;
-    int dtype;  // 0 f32, 1 bf16
+    int dtype;  // 0 f32, 1 bf16, 2 f16 (the reduced-precision raster)
     int B, Hb, Wb, Wp;
     float alpha_max;
     int TS;
@@ -181,6 +182,10 @@ hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st);
 // the pipelined one-tile-per-workgroup build (raster_pipe.hip)
 hipError_t launch_raster_fwd_pipe(const RasterArgs &a, hipStream_t st);
 hipError_t launch_raster_bwd_pipe(const RasterArgs &a, hipStream_t st);
+// the reduced-precision build (fp16 texels, packed fp16 bilinear blend), every launch form
+// (raster_f16.hip); the backward's parameter gradient must already be cleared
+hipError_t launch_raster_fwd_f16(const RasterArgs &a, hipStream_t st);
+hipError_t launch_raster_bwd_f16(const RasterArgs &a, hipStream_t st);
 hipError_t launch_fill0(float *p, long long n, hipStream_t st);
 hipError_t launch_loss_sum(const float *loss_tile, const ImgDev *imgs, int n_images, float *out,
                            hipStream_t st);

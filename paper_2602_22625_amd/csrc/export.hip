@@ -185,7 +185,8 @@ int dbmp_export_layers(dbmp_export_stream stream, const float *params, const int
     int HH = 0, WW = 0;
     if (N < 0 || B < 1 || Hb < 2 || Wb < 2 || !export_canvas(H, W, rho, &HH, &WW))
         return DBMP_EINVAL;
-    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16) return DBMP_EINVAL;
+    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16 && atlas_dtype != DBMP_F16)
+        return DBMP_EINVAL;
     if (!(alpha_max > 0.f && alpha_max <= 1.f)) return DBMP_EINVAL;
     if (max_w < 0 || max_h < 0 || max_w > WW || max_h > HH) return DBMP_EINVAL;
     if (N == 0) return DBMP_OK;
@@ -199,6 +200,10 @@ int dbmp_export_layers(dbmp_export_stream stream, const float *params, const int
     if (atlas_dtype == DBMP_F32)
         k_export_layers<float><<<grid, EXP_T * EXP_T, 0, st>>>(
             params, atlas_idx, B, (const float *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
+            alpha_out, colour_out);
+    else if (atlas_dtype == DBMP_F16)
+        k_export_layers<_Float16><<<grid, EXP_T * EXP_T, 0, st>>>(
+            params, atlas_idx, B, (const _Float16 *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
             alpha_out, colour_out);
     else
         k_export_layers<uint16_t><<<grid, EXP_T * EXP_T, 0, st>>>(

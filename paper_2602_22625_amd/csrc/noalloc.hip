@@ -115,7 +115,8 @@ extern "C" int dbmp_render_mse_noalloc(dbmp_stream stream, const float *params,
     // ---- host checks: nothing is enqueued and no HIP call is made before they pass ----
     if (N < 0 || H < 1 || W < 1 || (long long)H * W >= INT_MAX) return DBMP_EINVAL;
     if (!atlas || B < 1 || Hb < 2 || Wb < 2) return DBMP_EINVAL;
-    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16) return DBMP_EINVAL;
+    if (atlas_dtype != DBMP_F32 && atlas_dtype != DBMP_BF16 && atlas_dtype != DBMP_F16)
+        return DBMP_EINVAL;
     if (!bg || !target || !image || !status) return DBMP_EINVAL;
     if (N > 0 && (!params || !atlas_idx || !dL_dparams)) return DBMP_EINVAL;
     if (!(alpha_max > 0.f && alpha_max <= 1.f)) return DBMP_EINVAL;

@@ -1,6 +1,7 @@
 // Raster launches (Sec. 3.1.1-3.1.2; Supp. Eqs. S1-S5): the kernels are in raster_kernels.h.
 // This file builds the one-tile-per-workgroup and persistent forms; raster_pipe.hip builds the
-// pipelined one-tile-per-workgroup form (a separate translation unit, compiled in parallel).
+// pipelined one-tile-per-workgroup form and raster_f16.hip every form of the fp16 build
+// (separate translation units, compiled in parallel).
 #include "raster_kernels.h"
 
 namespace dbmp {
@@ -30,16 +31,9 @@ __global__ void __launch_bounds__(256) k_loss_sum(const float *__restrict__ lt,
     if (threadIdx.x == 0) out[blockIdx.x] = (float)s[0];
 }
 
-// The pipelined walks pay off where the launch leaves SIMDs with few waves: at most 4 waves per
-// SIMD (16 per compute unit) across the one-tile-per-workgroup grid.
-static bool pipelined(const RasterArgs &a)
-{
-    const long long waves = (long long)a.n_tiles * (a.TS * a.TS / 64);
-    return a.sched != SCHED_PERSISTENT && waves <= 16LL * a.n_cu;
-}
-
 hipError_t launch_raster_fwd(const RasterArgs &a, hipStream_t st)
 {
+    if (a.dtype == 2) return launch_raster_fwd_f16(a, st);
     if (a.n_tiles > 0) {
         if (a.sched == SCHED_PERSISTENT) raster_fwd_build<LAUNCH_PERSISTENT>(a, st);
         else if (pipelined(a)) return launch_raster_fwd_pipe(a, st);
@@ -53,6 +47,7 @@ hipError_t launch_raster_bwd(const RasterArgs &a, hipStream_t st)
     if (a.n_param_floats > 0)
         k_fill0<<<(unsigned)((a.n_param_floats + 255) / 256), 256, 0, st>>>(a.dparams,
                                                                              a.n_param_floats);
+    if (a.dtype == 2) return launch_raster_bwd_f16(a, st);
     if (a.n_tiles > 0) {
         if (a.sched == SCHED_PERSISTENT) raster_bwd_build<LAUNCH_PERSISTENT>(a, st);
         else if (pipelined(a)) return launch_raster_bwd_pipe(a, st);

@@ -45,6 +45,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dbmp {
 
@@ -129,6 +130,18 @@ struct Cell {
     float wu, wv;             // fractional position inside the cell
 };
 
+// The reduced-precision build (fp16 texels, Sec. 3.1.2's half-precision path): the two texels of
+// a cell row are adjacent, so each row is one 4-byte load (gfx950 serves unaligned dword loads),
+// and the pair stays packed for the blend. The weights are packed too, rounded toward zero.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+template <>
+struct Cell<_Float16> {
+    half2v A, B;  // (p00, p01) and (p10, p11)
+    half2v w;     // (wu, wv)
+};
+template <typename TexT>
+constexpr bool is_f16 = std::is_same<TexT, _Float16>::value;
+
 // A lane outside the support (in = false) reads the all-zero cell that follows the padded
 // atlas (element offset zcell), so M = MU = MV = 0 there exactly whatever its weights: one
 // select of the address, no select of the weights. The cell is addressed by its 32-bit byte
@@ -143,8 +156,13 @@ __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restri
                                              int tex, int Wp, double U, double V, bool in,
                                              int zcell)
 {
-    c.wu = (float)__builtin_amdgcn_fract(U);
-    c.wv = (float)__builtin_amdgcn_fract(V);
+    const float wu = (float)__builtin_amdgcn_fract(U), wv = (float)__builtin_amdgcn_fract(V);
+    if constexpr (is_f16<TexT>)
+        c.w = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(wu, wv));
+    else {
+        c.wu = wu;
+        c.wv = wv;
+    }
     const unsigned at = in ? (unsigned)tex + __umul24((unsigned)(int)V, (unsigned)Wp) +
                                  (unsigned)(int)U
                            : (unsigned)zcell;
@@ -158,10 +176,15 @@ __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restri
     const unsigned b0 = at * (unsigned)sizeof(TexT);
     GTex *t0 = (GTex *)(base + b0);
     GTex *t1 = (GTex *)(base + (b0 + (unsigned)Wp * sizeof(TexT)));
-    c.p00 = t0[0];
-    c.p01 = t0[1];
-    c.p10 = t1[0];
-    c.p11 = t1[1];
+    if constexpr (is_f16<TexT>) {  // merged by the compiler into one dword load per row
+        c.A = half2v{t0[0], t0[1]};
+        c.B = half2v{t1[0], t1[1]};
+    } else {
+        c.p00 = t0[0];
+        c.p01 = t0[1];
+        c.p10 = t1[0];
+        c.p11 = t1[1];
+    }
     // no instruction and no wait: only an ordering point for the compiler
     if constexpr (PIN) asm volatile("" ::: "memory");
 }
@@ -171,20 +194,53 @@ __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restri
 template <typename TexT>
 __device__ __forceinline__ void drop_cell(const Cell<TexT> &c)
 {
-    asm volatile("" ::"v"(c.p00), "v"(c.p01), "v"(c.p10), "v"(c.p11));
+    if constexpr (is_f16<TexT>)
+        asm volatile("" ::"v"(c.A), "v"(c.B));
+    else
+        asm volatile("" ::"v"(c.p00), "v"(c.p01), "v"(c.p10), "v"(c.p11));
 }
 
+// The bilinear value M and its derivatives M_U, M_V of one sample: float32, or (fp16 build) the
+// two packed registers the blend leaves, W = (M, M_V) and Z = (M_U, unused), widened on use.
 template <typename TexT>
-__device__ __forceinline__ void blend(const Cell<TexT> &c, float &M, float &MU, float &MV)
+struct Bil {
+    float M, MU, MV;
+    __device__ float m() const { return M; }
+    __device__ float mu() const { return MU; }
+    __device__ float mv() const { return MV; }
+};
+template <>
+struct Bil<_Float16> {
+    half2v W, Z;
+    __device__ float m() const { return (float)W.x; }
+    __device__ float mu() const { return (float)Z.x; }
+    __device__ float mv() const { return (float)W.y; }
+};
+
+template <typename TexT>
+__device__ __forceinline__ Bil<TexT> blend(const Cell<TexT> &c)
 {
-    const float p00 = texel<TexT>(c.p00), p01 = texel<TexT>(c.p01);
-    const float p10 = texel<TexT>(c.p10), p11 = texel<TexT>(c.p11);
-    const float d0 = p01 - p00, d1 = p11 - p10;
-    const float top = fmaf(c.wu, d0, p00);
-    const float bot = fmaf(c.wu, d1, p10);
-    MV = bot - top;
-    M = fmaf(c.wv, MV, top);
-    MU = fmaf(c.wv, d1 - d0, d0);
+    Bil<TexT> b;
+    if constexpr (is_f16<TexT>) {
+        // packed fp16 (v_pk_fma_f16): interpolate both columns along V' first, then along U'
+        const half2v wu = {c.w.x, c.w.x}, wv = {c.w.y, c.w.y};
+        const half2v E = c.B - c.A;                             // (p10 - p00, p11 - p01)
+        const half2v R = __builtin_elementwise_fma(wv, E, c.A);  // the column values at V'
+        const half2v X = __builtin_shufflevector(R, E, 0, 2);
+        const half2v Y = __builtin_shufflevector(R, E, 1, 3);
+        b.Z = Y - X;                                             // (M_U, e1 - e0)
+        b.W = __builtin_elementwise_fma(wu, b.Z, X);             // (M, M_V)
+    } else {
+        const float p00 = texel<TexT>(c.p00), p01 = texel<TexT>(c.p01);
+        const float p10 = texel<TexT>(c.p10), p11 = texel<TexT>(c.p11);
+        const float d0 = p01 - p00, d1 = p11 - p10;
+        const float top = fmaf(c.wu, d0, p00);
+        const float bot = fmaf(c.wu, d1, p10);
+        b.MV = bot - top;
+        b.M = fmaf(c.wv, b.MV, top);
+        b.MU = fmaf(c.wv, d1 - d0, d0);
+    }
+    return b;
 }
 
 // Visits per wave whose bilinear values the fused step keeps for its backward (3 vector
@@ -200,6 +256,15 @@ __device__ __forceinline__ void blend(const Cell<TexT> &c, float &M, float &MU, 
 // (twelve spill scalar registers).
 #ifndef STORED_VISITS_PIPE
 #define STORED_VISITS_PIPE 10
+#endif
+// The fp16 build keeps a visit in 2 vector registers instead of 3 (its entry index takes a
+// scalar register either way): 7 keep the fused 16 x 16 kernel at 72 vector registers, 7 waves
+// per SIMD, and the pipelined build stays without scalar spills up to 10 (80 registers).
+#ifndef STORED_VISITS_F16
+#define STORED_VISITS_F16 7
+#endif
+#ifndef STORED_VISITS_PIPE_F16
+#define STORED_VISITS_PIPE_F16 10
 #endif
 
 // Lists up to this length are sorted in LDS, longer ones in place in global memory. At 512
@@ -349,9 +414,9 @@ __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__r
 // texels of those visits; it only recomputes U', V' for the geometric terms. Lanes outside a
 // visit's support sampled the all-zero cell, so their stored values are exactly 0. SV = 1 with
 // n = 0 is the form that stores nothing.
-template <int SV>
+template <int SV, typename TexT>
 struct Stored {
-    float M[SV], MU[SV], MV[SV];
+    Bil<TexT> b[SV];
     int e[SV];
     int n = 0;     // visits stored
     int last = -1; // the last stored visit's batch entry (visits go in ascending entry order)
@@ -364,7 +429,8 @@ struct Stored {
 // The backward's walk over a tile's sorted list (defined below, after the forward kernel that
 // also runs it in the fused fit step).
 template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, int SV, typename IdAt>
-__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged, const Stored<SV> &st,
+__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
+                                         const Stored<SV, TexT> &st,
                                          PrimRec *__restrict__ s_rec,
                                          float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
@@ -393,8 +459,11 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
     constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT, PIPE = LAUNCH == LAUNCH_TILE_PIPE;
     // the fused step keeps its first visits' bilinear values for the backward (the pipelined
     // build runs where the grid leaves SIMDs with few waves, so registers are not its limit)
-    constexpr int SVN = LAUNCH == LAUNCH_TILE ? STORED_VISITS
-                        : LAUNCH == LAUNCH_TILE_PIPE ? STORED_VISITS_PIPE : 0;
+    constexpr int SVN = LAUNCH == LAUNCH_TILE
+                            ? (is_f16<TexT> ? STORED_VISITS_F16 : STORED_VISITS)
+                        : LAUNCH == LAUNCH_TILE_PIPE
+                            ? (is_f16<TexT> ? STORED_VISITS_PIPE_F16 : STORED_VISITS_PIPE)
+                            : 0;
     constexpr bool STORE = FUSED && SVN > 0;
     constexpr int SV = STORE ? SVN : 1;
     // A fit step's Adam state {updates applied, unused, gradient pending, unused}: this step's
@@ -515,11 +584,9 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
             T = T * (1.f - a);
         };
         auto over = [&](int j, const PrimRec &r, const Cell<TexT> &c, uint64_t m) {
-            float M, MU, MV;
-            blend<TexT>(c, M, MU, MV);
-            over_m(j, r, M, m);
+            over_m(j, r, blend<TexT>(c).m(), m);
         };
-        Stored<SV> st;
+        Stored<SV, TexT> st;
         auto composite = [&](auto id_at) {
             for (int b0 = 0; b0 < n; b0 += BATCH) {
                 const int cnt = min(BATCH, n - b0);
@@ -543,19 +610,17 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                 if (ea < 0) break;
                                 const int eb = find_req(hits, cb, mb);
                                 {
-                                    float M, MU, MV;
-                                    blend<TexT>(ca, M, MU, MV);
-                                    over_m(b0 + ea, s_rec[ea], M, ma);
-                                    st.M[v] = M; st.MU[v] = MU; st.MV[v] = MV;
+                                    const Bil<TexT> b = blend<TexT>(ca);
+                                    over_m(b0 + ea, s_rec[ea], b.m(), ma);
+                                    st.b[v] = b;
                                     st.e[v] = ea; st.n = v + 1; st.last = ea;
                                 }
                                 if (eb < 0) { drop_cell(cb); ea = -1; break; }
                                 ea = find_req(hits, ca, ma);
                                 {
-                                    float M, MU, MV;
-                                    blend<TexT>(cb, M, MU, MV);
-                                    over_m(b0 + eb, s_rec[eb], M, mb);
-                                    st.M[v + 1] = M; st.MU[v + 1] = MU; st.MV[v + 1] = MV;
+                                    const Bil<TexT> b = blend<TexT>(cb);
+                                    over_m(b0 + eb, s_rec[eb], b.m(), mb);
+                                    st.b[v + 1] = b;
                                     st.e[v + 1] = eb; st.n = v + 2; st.last = eb;
                                 }
                             }
@@ -585,12 +650,9 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                 request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V,
                                                           __builtin_amdgcn_inverse_ballot_w64(m),
                                                           zcell);
-                                float M, MU, MV;
-                                blend<TexT>(c, M, MU, MV);
-                                over_m(b0 + e, r, M, m);
-                                st.M[v] = M;
-                                st.MU[v] = MU;
-                                st.MV[v] = MV;
+                                const Bil<TexT> b = blend<TexT>(c);
+                                over_m(b0 + e, r, b.m(), m);
+                                st.b[v] = b;
                                 st.e[v] = e;
                                 st.n = v + 1;
                                 st.last = e;
@@ -609,9 +671,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                         if (__builtin_amdgcn_inverse_ballot_w64(m)) {  // the support lanes only
                             Cell<TexT> c;
                             request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V, true, zcell);
-                            float M, MU, MV;
-                            blend<TexT>(c, M, MU, MV);
-                            const float a = r.ka * M;  // Eq. (3)
+                            const float a = r.ka * blend<TexT>(c).m();  // Eq. (3)
                             if (T >= DBMP_TAU) { K = b0 + e; TK = T; }
                             const float w = T * a;
                             C0 = fmaf(w, r.cr, C0);
@@ -674,7 +734,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                       lane);
         else
             bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return ((volatile int *)seg)[j]; },
-                                      staged, Stored<1>(), s_rec, s_grad, recs, atlas, Wp, zcell, tg, vmask,
+                                      staged, Stored<1, TexT>(), s_rec, s_grad, recs, atlas, Wp, zcell, tg, vmask,
                                       g0,
                                       g1, g2,
                                       0.f, b0, b1, b2, tg.valid ? K : -1, TK, dparams, cu1, cv1,
@@ -715,7 +775,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 // instead saves two instructions but cancels, and it was measured to lose about two decimal
 // digits on the angle's gradient.
 template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, int SV, typename IdAt>
-__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged, const Stored<SV> &st,
+__device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
+                                         const Stored<SV, TexT> &st,
                                          PrimRec *__restrict__ s_rec,
                                          float *__restrict__ s_grad,
                                          const PrimRec *__restrict__ recs,
@@ -798,9 +859,8 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged, const S
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     auto under = [&](int e, int j, const Cell<TexT> &c, float Ub, float Vb) {
-        float M, MU, MV;
-        blend<TexT>(c, M, MU, MV);
-        under_m(e, j, M, MU, MV, Ub, Vb);
+        const Bil<TexT> b = blend<TexT>(c);
+        under_m(e, j, b.m(), b.mu(), b.mv(), Ub, Vb);
     };
     for (int hi = n; hi > 0; hi -= BATCH) {
         const int b0 = max(0, hi - BATCH), cnt = hi - b0;
@@ -850,7 +910,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged, const S
                 const PrimRec &r = s_rec[e];
                 const double U = fma(r.aU, xd, fma(r.bU, yd, r.eU));
                 const double V = fma(r.aV, xd, fma(r.bV, yd, r.eV));
-                under_m(e, b0 + e, st.M[v], st.MU[v], st.MV[v], (float)(U - cu1),
+                under_m(e, b0 + e, st.b[v].m(), st.b[v].mu(), st.b[v].mv(), (float)(U - cu1),
                         (float)(V - cv1));
             }
         }
@@ -930,7 +990,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
         }
         const int *seg = lists + (size_t)tile * list_cap;
         bwd_walk<TS * TS, TexT, HAS_GA, PIPE>(n, [&](int j) { return seg[j]; }, false,
-                                              Stored<1>(), s_rec,
+                                              Stored<1, TexT>(), s_rec,
                                               s_grad,
                                         recs,
                                         atlas, Wp, zcell, tg, vmask, g0, g1, g2, ga, G0, G1, G2,
@@ -953,6 +1013,14 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
 // ------------------------------------------------------------------------------------------
 // Host side: launch of one kernel build (LAUNCH as above), dispatched over the runtime choices
 // ------------------------------------------------------------------------------------------
+// The pipelined walks pay off where the launch leaves SIMDs with few waves: at most 4 waves per
+// SIMD (16 per compute unit) across the one-tile-per-workgroup grid.
+static inline bool pipelined(const RasterArgs &a)
+{
+    const long long waves = (long long)a.n_tiles * (a.TS * a.TS / 64);
+    return a.sched != SCHED_PERSISTENT && waves <= 16LL * a.n_cu;
+}
+
 // Launches `kern`; with timing events armed, through hipExtLaunchKernel, which has the device
 // record them when the kernel starts and when it ends.
 template <typename K, typename... Args>

@@ -17,7 +17,9 @@ def _dtype_code(atlas: torch.Tensor) -> int:
         return capi.DBMP_F32
     if atlas.dtype == torch.bfloat16:
         return capi.DBMP_BF16
-    raise TypeError("atlas must be float32 or bfloat16, got %s" % atlas.dtype)
+    if atlas.dtype == torch.float16:  # the reduced-precision raster
+        return capi.DBMP_F16
+    raise TypeError("atlas must be float32, bfloat16 or float16, got %s" % atlas.dtype)
 
 
 def _need(t, name, dtype=None, shape=None):

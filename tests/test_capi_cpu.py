@@ -25,6 +25,16 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_header_atlas_dtypes_match_the_binding():
+    """The atlas element types of diffbmp.h, float16 selecting the reduced-precision raster."""
+    import re
+    text = open(capi.HEADER).read()
+    m = re.search(r"typedef enum \{([^}]*)\} dbmp_dtype;", text)
+    vals = dict((k.strip(), int(v)) for k, v in (e.split("=") for e in m.group(1).split(",")))
+    assert vals == {"DBMP_F32": capi.DBMP_F32, "DBMP_BF16": capi.DBMP_BF16,
+                    "DBMP_F16": capi.DBMP_F16}
+
+
 def test_library_exports_every_declared_symbol():
     lib = capi.load()
     for n in header_functions() + header_functions(capi.HEADER_CNN):
@@ -118,6 +128,9 @@ def test_noalloc_host_checks_need_no_device():
     assert lib.dbmp_render_mse_noalloc(*bad) == capi.DBMP_EINVAL
     bad = list(args)
     bad[15] = 0     # list capacity
+    assert lib.dbmp_render_mse_noalloc(*bad) == capi.DBMP_EINVAL
+    bad = list(args)
+    bad[8] = 3      # atlas dtype: DBMP_F32, DBMP_BF16 and DBMP_F16 only
     assert lib.dbmp_render_mse_noalloc(*bad) == capi.DBMP_EINVAL
     big = list(args)
     big[9] = big[10] = 4096  # 4096 x 4096: 128 MiB of per-pixel state alone

@@ -431,16 +431,17 @@ def test_pipelined_and_single_cell_walks_agree():
     keep a second cell in flight; a larger one runs them one cell at a time. The same 512 x 512
     image (4,096 waves at 8 x 8, 16 x 16 and 32 x 32 tiles) rendered alone and as the first
     image of a batch with a 1024 x 1024 canvas: images bitwise equal, fused-step gradients
-    within 1e-5 per column (atomics in another order), for the float32 and bfloat16 atlases."""
+    within 1e-5 per column (atomics in another order), for the float32, bfloat16 and float16
+    atlases (the last the reduced-precision build)."""
     from paper_2602_22625_amd.render import Renderer
     d = synth.make_workload("c1")
     dev = torch.device("cuda")
     t = torch.tensor(d["target"], device=dev)
     N = d["params"].shape[0]
-    for bf16 in (False, True):
+    for bf16 in (False, True, "f16"):
         p, idx, a = to_dev(d)
         if bf16:
-            a = a.to(torch.bfloat16)
+            a = a.to(torch.float16 if bf16 == "f16" else torch.bfloat16)
         P2 = torch.cat([p, p]).contiguous()
         I2 = torch.cat([idx, idx]).contiguous()
         bg = torch.ones(2, 3, device=dev)
@@ -499,13 +500,14 @@ def _long_and_deep_scenes():
     yield "long", 64, lng, np.zeros(N, dtype=np.int32), synth.soft_disk(32)[None], (1, 1, 1)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
 @pytest.mark.parametrize("tile", [8, 32])
-def test_walk_builds_agree_on_deep_and_long_lists(tile):
+def test_walk_builds_agree_on_deep_and_long_lists(tile, dtype):
     """The deep-stack and long-list scenes rendered alone (a launch of few waves: the pipelined
     walks) and as the first image of a batch with a 1024 x 1024 canvas (the one-cell walks), over
     several batches of staged records and the LDS and global-memory sort paths: images bitwise
     equal; the backward with dL/dI and dL/dA on the first image only, within 1e-5 of each
-    column's scale."""
+    column's scale. dtype f16: the reduced-precision build."""
     from paper_2602_22625_amd.render import Renderer
     dev = torch.device("cuda")
     for name, S, params, idx, atlas, bg in _long_and_deep_scenes():
@@ -513,6 +515,8 @@ def test_walk_builds_agree_on_deep_and_long_lists(tile):
         p = torch.tensor(params, device=dev)
         i_t = torch.tensor(idx, device=dev)
         a = torch.tensor(atlas, device=dev)
+        if dtype == "f16":
+            a = a.to(torch.float16)
         bg1 = torch.tensor(np.asarray(bg, dtype=np.float32), device=dev)
         R1, R2 = Renderer(), Renderer()
         i1, a1 = R1.render(p, i_t, a, S, S, bg1, 1.0, tile)
