@@ -83,12 +83,14 @@ def load_workload(name, synth, np, torch, dev):
     return wl, d, p0, idx, atlas, target
 
 
-def held_fit(Fitter, capi, wl, p0, idx, atlas, target, schedule, chunk, pre_steps=0):
+def held_fit(Fitter, capi, wl, p0, idx, atlas, target, schedule, chunk, pre_steps=0,
+             placement=0):
     """A fit whose graph holds the state: its base parameters are those after `pre_steps` plain
     steps (the initial ones for 0); one eager step from there leaves a gradient pending, so every
     held step runs the full work (the Adam update included)."""
     fit = Fitter(p0, idx, atlas, target, tile=wl.tile, lr=1e-2)
     fit.set_launch(wl.tile, schedule)
+    fit.R.set_atlas_placement(placement)
     fit._size()
     if pre_steps:
         fit.capture(10)
@@ -332,6 +334,10 @@ def main():
         log("c1: %.4f ms/step, %.3e evals/s" % (1e3 * w1 / 100, pr1 / w1))
         del f1
 
+    # ---------------- texels from LDS against texels through the caches -------------------------
+    if not args.no_c1:
+        extra["atlas_in_lds_ab"] = bench_atlas_lds(capi, synth, Fitter, np, torch, dev)
+
     # ---------------- 64 independent fits advanced as one batch -----------------------------------
     if not args.no_c3:
         extra["c3_64_fits"] = bench_c3(args, synth, capi, autotune, BatchFitter, Fitter, np,
@@ -399,6 +405,38 @@ def bench_f16(args, capi, metrics, Fitter, wl, d, p0, idx, target, k_bf16, extra
             "after_100_steps": {"ms_per_step": round(1e3 * w100 / 50, 5),
                                 "evals_per_s": round(p100 / w100), "psnr": round(psnr100, 3),
                                 "bf16_psnr": extra.get("c2_after_100_steps", {}).get("psnr")}}
+
+
+def bench_atlas_lds(capi, synth, Fitter, np, torch, dev):
+    """The fused fit-step kernel with its texels read from an LDS copy of the padded atlas
+    (dbmp_set_atlas_placement) against the default path through L1/L2, on the two workloads
+    whose atlas fits: 128x128 with 64 primitives on one 32x32 disk (4.6 KB), and the 512x512
+    workload with its 4,096 primitives all on one 64x64 bitmap (17.9 KB). Both run the
+    pipelined build; held state, sorted tiles, 200 launches each."""
+    out = {}
+    d0 = synth.make_workload("c0")
+    d1 = synth.make_workload("c1")
+    cases = {"128sq_64prims_disk32": ("c0", d0["params"], d0["idx"], d0["atlas"], d0["target"]),
+             "512sq_4096prims_one_64x64_bitmap": ("c1", d1["params"], np.zeros_like(d1["idx"]),
+                                                  d1["atlas"][:1].copy(), d1["target"])}
+    for name, (wname, params, idx, atlas, target) in cases.items():
+        wl = synth.WORKLOADS[wname]
+        p0 = torch.tensor(params, device=dev)
+        i_t = torch.tensor(idx, device=dev)
+        a = torch.tensor(atlas, device=dev)
+        t = torch.tensor(target, device=dev)
+        row = {}
+        for place, key in ((capi.DBMP_ATLAS_GLOBAL, "l1_l2_us"), (capi.DBMP_ATLAS_LDS, "lds_us")):
+            fit, _ = held_fit(Fitter, capi, wl, p0, i_t, a, t, capi.DBMP_SCHED_SORTED, 10,
+                              placement=place)
+            time_steps(fit, capi, torch, 20, 10, 10)
+            k, _ = fused_kernel_time(fit, capi, np, torch, 200)
+            row[key] = round(k * 1e6, 2)
+            del fit
+        row["lds_speedup"] = round(row["l1_l2_us"] / row["lds_us"], 4)
+        out[name] = row
+        log("atlas A/B %s: L1/L2 %.2f us, LDS %.2f us" % (name, row["l1_l2_us"], row["lds_us"]))
+    return out
 
 
 def bench_c3(args, synth, capi, autotune, BatchFitter, Fitter, np, torch, dev):

@@ -61,6 +61,8 @@ typedef enum {
 
 typedef enum { DBMP_F32 = 0, DBMP_BF16 = 1, DBMP_F16 = 2 } dbmp_dtype;
 
+#define DBMP_DEFAULT_TILE 16 /* the tile a call given tile = 0 uses */
+
 /* Creates a context on HIP device `device`. The context owns the workspace (per-primitive
  * records, the per-tile primitive lists, the padded atlas and the per-pixel state the backward
  * needs) and grows it on demand. Every screen tile gets a list of `list_capacity` entries
@@ -100,6 +102,22 @@ typedef enum { DBMP_SCHED_GRID = 0, DBMP_SCHED_SORTED = 1, DBMP_SCHED_PERSISTENT
 int dbmp_set_schedule(dbmp_ctx *ctx, int schedule, int workgroups_per_cu, int items_per_grab);
 
 /*
+ * Where the raster kernels read texels (Sec. 3.1.2 stages primitive templates in on-chip shared
+ * memory):
+ *   DBMP_ATLAS_GLOBAL  the padded atlas in device memory, through the L1 and L2 caches (default);
+ *   DBMP_ATLAS_LDS     every workgroup first copies the whole padded atlas,
+ *                      B (Hb + 2)(Wb + 2) + 2 (Wb + 2) texels, into LDS and samples that copy;
+ *                      taken by launches of the pipelined build (at most 16 waves per compute
+ *                      unit: small canvases) when the copy takes at most
+ *                      DBMP_ATLAS_LDS_MAX_BYTES; other launches read device memory.
+ * Results are bit-identical either way (the gradient up to the order of its float atomics).
+ * Host-only; applies to the forwards that follow (and their backwards).
+ */
+typedef enum { DBMP_ATLAS_GLOBAL = 0, DBMP_ATLAS_LDS = 1 } dbmp_atlas_placement;
+#define DBMP_ATLAS_LDS_MAX_BYTES 32768
+int dbmp_set_atlas_placement(dbmp_ctx *ctx, int placement);
+
+/*
  * Measurement hook: the next raster kernel launch of `stage` on this context (0: the forward
  * compositing kernel of dbmp_render / dbmp_render_batched; 1: the backward kernel of
  * dbmp_render_backward / dbmp_render_backward_mse) is launched so that the device records
@@ -128,7 +146,10 @@ int dbmp_set_atlas(dbmp_ctx *ctx, dbmp_stream stream, const void *atlas, int B, 
  *   H, W                      canvas size, >= 1.
  *   bg                        device float32: 3 values, or [3, H, W] when bg_per_pixel != 0.
  *   alpha_max                 in (0, 1] (Eq. 3).
- *   tile                      screen tile edge in pixels: 8, 16 or 32.
+ *   tile                      screen tile edge in pixels: 8, 16 or 32, or 0 for the library's
+ *                             choice, DBMP_DEFAULT_TILE (the fastest on every measured workload,
+ *                             128x128 to 2048x2048 and batches of uneven canvases; the Python
+ *                             autotuner times the candidates for a given workload instead).
  *   image                     out, device float32 [3, H, W].
  *   alpha                     out, device float32 [H, W], A = 1 - T_N; may be NULL.
  * The context keeps what dbmp_render_backward needs (no per-layer state: the backward

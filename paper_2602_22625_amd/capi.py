@@ -16,6 +16,8 @@ DBMP_OK, DBMP_EINVAL, DBMP_ENOMEM, DBMP_EHIP, DBMP_EOVERFLOW, DBMP_ESTATE, DBMP_
     0, -1, -2, -3, -4, -5, -6
 DBMP_F32, DBMP_BF16, DBMP_F16 = 0, 1, 2
 DBMP_SCHED_GRID, DBMP_SCHED_SORTED, DBMP_SCHED_PERSISTENT = 0, 1, 2
+DBMP_ATLAS_GLOBAL, DBMP_ATLAS_LDS = 0, 1
+DBMP_ATLAS_LDS_MAX_BYTES = 32768
 DBMP_NOALLOC_SCRATCH_MB = 64  # include/diffbmp.h
 STATUS_NAMES = {0: "DBMP_OK", -1: "DBMP_EINVAL", -2: "DBMP_ENOMEM", -3: "DBMP_EHIP",
                 -4: "DBMP_EOVERFLOW", -5: "DBMP_ESTATE", -6: "DBMP_ENONFINITE"}
@@ -53,6 +55,7 @@ def load():
         "dbmp_destroy": ([P], I),
         "dbmp_reserve": ([P, LL], I),
         "dbmp_set_schedule": ([P, I, I, I], I),
+        "dbmp_set_atlas_placement": ([P, I], I),
         "dbmp_time_next_launch": ([P, I, P, P], I),
         "dbmp_set_atlas": ([P, P, P, I, I, I, I], I),
         "dbmp_render": ([P, P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, P, P], I),
@@ -136,6 +139,10 @@ def dbmp_reserve(ctx, list_capacity):
 def dbmp_set_schedule(ctx, schedule, workgroups_per_cu=4, items_per_grab=1):
     return _chk(ctx, load().dbmp_set_schedule(ctx, int(schedule), int(workgroups_per_cu),
                                               int(items_per_grab)))
+
+
+def dbmp_set_atlas_placement(ctx, placement):
+    return _chk(ctx, load().dbmp_set_atlas_placement(ctx, int(placement)))
 
 
 def dbmp_time_next_launch(ctx, stage, start_event, stop_event):

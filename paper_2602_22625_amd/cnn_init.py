@@ -112,6 +112,27 @@ def train_flops_per_image():
     return float(sum(2 * m * n * k for m, n, k in fwd + bwd))
 
 
+def conv_roofline_seconds_per_image(train=True, peak_flops=2.5e15, hbm_bytes_per_s=8e12):
+    """Lower bound on the convolution layers' time per image: each product takes the longer of
+    its matrix-core time at the dense bf16 peak and its HBM time for the activations it must
+    read and write once (bf16: input and output maps; the input gradient also reads the ReLU
+    mask). The dense head is a few MFLOP and left out."""
+    t = 0.0
+    s = IMG
+    for l, (ci, co) in enumerate(CONV):
+        o = s // 2
+        flop = 2.0 * o * o * co * 9 * ci
+        x, y = 2.0 * s * s * ci, 2.0 * o * o * co
+        prods = [(flop, x + y)]                  # forward: read x, write y
+        if train:
+            prods.append((flop, x + y))          # weight gradient: read x and dy
+            if l > 0:
+                prods.append((flop, y + 2 * x))  # input gradient: read dy and the mask, write dx
+        t += sum(max(f / peak_flops, b / hbm_bytes_per_s) for f, b in prods)
+        s = o
+    return t
+
+
 # ------------------------------------------------------------------------------------------
 # Network
 # ------------------------------------------------------------------------------------------

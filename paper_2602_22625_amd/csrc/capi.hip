@@ -29,6 +29,7 @@ struct dbmp_ctx {
     int wgs_per_cu = 4;
     int grab = 1;
     int n_cu = 256;
+    int atlas_place = DBMP_ATLAS_GLOBAL;  // dbmp_set_atlas_placement
     // one-shot timing events for the next raster launch of each stage (0 forward, 1 backward)
     hipEvent_t time_ev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     // the padded atlas held in atlas_pad (set by dbmp_set_atlas or a render given an atlas)
@@ -194,8 +195,9 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     if (!bg) return fail(c, DBMP_EINVAL, "bg is NULL");
     if (!(alpha_max > 0.f && alpha_max <= 1.f))
         return fail(c, DBMP_EINVAL, "alpha_max must be in (0, 1]");
+    if (tile == 0) tile = DBMP_DEFAULT_TILE;
     if (tile != 8 && tile != 16 && tile != 32)
-        return fail(c, DBMP_EINVAL, "tile must be 8, 16 or 32");
+        return fail(c, DBMP_EINVAL, "tile must be 8, 16, 32 or 0");
     if (!image) return fail(c, DBMP_EINVAL, "image is NULL");
     int rc;
     if (atlas) {
@@ -295,6 +297,11 @@ int render_impl(dbmp_ctx *c, hipStream_t st, const std::vector<dbmp_image_desc> 
     ra.n_images = (int)ni; ra.n_tiles = (int)tiles;
     ra.atlas_pad = c->atlas_pad.p; ra.dtype = dtype; ra.Wp = Wp; ra.Hb = Hb; ra.Wb = Wb;
     ra.zcell = (int)zero_cell(B, Hb, Wb);
+    {
+        const long long bytes = (dtype == DBMP_F32 ? 4LL : 2LL) * padded_atlas_elems(B, Hb, Wb);
+        ra.atlas_lds_bytes =
+            c->atlas_place == DBMP_ATLAS_LDS && bytes <= DBMP_ATLAS_LDS_MAX_BYTES ? (int)bytes : 0;
+    }
     ra.bg = bg; ra.bg_pp = bg_pp; ra.image = image; ra.alpha = alpha;
     ra.saveK = (int *)c->saveK.p; ra.saveT = (float *)c->saveT.p;
     ra.flags = (const int *)c->flags.p; ra.TS = tile;
@@ -408,6 +415,15 @@ int dbmp_time_next_launch(dbmp_ctx *c, int stage, void *start_event, void *stop_
         return fail(c, DBMP_EINVAL, "give both events or neither");
     c->time_ev[stage][0] = (hipEvent_t)start_event;
     c->time_ev[stage][1] = (hipEvent_t)stop_event;
+    return DBMP_OK;
+}
+
+int dbmp_set_atlas_placement(dbmp_ctx *c, int placement)
+{
+    if (!c) return DBMP_EINVAL;
+    if (placement != DBMP_ATLAS_GLOBAL && placement != DBMP_ATLAS_LDS)
+        return fail(c, DBMP_EINVAL, "unknown atlas placement");
+    c->atlas_place = placement;
     return DBMP_OK;
 }
 

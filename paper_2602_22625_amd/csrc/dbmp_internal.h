@@ -143,6 +143,8 @@ struct RasterArgs {
     const void *atlas_pad;
     int dtype, Wp, Hb, Wb;
     int zcell;                         // element offset of the padded atlas's all-zero cell
+    int atlas_lds_bytes;               // > 0: the pipelined build stages this many bytes of the
+                                       // padded atlas in LDS (dbmp_set_atlas_placement)
     const float *bg;
     int bg_pp;
     float *image, *alpha;

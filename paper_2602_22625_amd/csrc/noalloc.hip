@@ -120,6 +120,7 @@ extern "C" int dbmp_render_mse_noalloc(dbmp_stream stream, const float *params,
     if (!bg || !target || !image || !status) return DBMP_EINVAL;
     if (N > 0 && (!params || !atlas_idx || !dL_dparams)) return DBMP_EINVAL;
     if (!(alpha_max > 0.f && alpha_max <= 1.f)) return DBMP_EINVAL;
+    if (tile == 0) tile = DBMP_DEFAULT_TILE;
     if (tile != 8 && tile != 16 && tile != 32) return DBMP_EINVAL;
     if (list_capacity < 1 || list_capacity >= (1 << 24)) return DBMP_EINVAL;
     const size_t esz = atlas_dtype == DBMP_F32 ? 4 : 2;

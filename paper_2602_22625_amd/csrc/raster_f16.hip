@@ -30,6 +30,7 @@ hipError_t launch_raster_fwd_f16(const RasterArgs &a, hipStream_t st)
 {
     if (a.n_tiles > 0) {
         if (a.sched == SCHED_PERSISTENT) f16_fwd<LAUNCH_PERSISTENT>(a, st);
+        else if (pipelined(a) && a.atlas_lds_bytes > 0) f16_fwd<LAUNCH_TILE_PIPE_LDS>(a, st);
         else if (pipelined(a)) f16_fwd<LAUNCH_TILE_PIPE>(a, st);
         else f16_fwd<LAUNCH_TILE>(a, st);
     }
@@ -40,6 +41,7 @@ hipError_t launch_raster_bwd_f16(const RasterArgs &a, hipStream_t st)
 {
     if (a.n_tiles > 0) {
         if (a.sched == SCHED_PERSISTENT) f16_bwd<LAUNCH_PERSISTENT>(a, st);
+        else if (pipelined(a) && a.atlas_lds_bytes > 0) f16_bwd<LAUNCH_TILE_PIPE_LDS>(a, st);
         else if (pipelined(a)) f16_bwd<LAUNCH_TILE_PIPE>(a, st);
         else f16_bwd<LAUNCH_TILE>(a, st);
     }

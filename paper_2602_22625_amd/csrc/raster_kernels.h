@@ -151,7 +151,8 @@ constexpr bool is_f16 = std::is_same<TexT, _Float16>::value;
 // is the truncation.
 // PIN (pipelined walks): the loads stay where they are issued, ahead of the other cell's
 // arithmetic, instead of being moved down to their first use by the compiler.
-template <typename TexT, bool PIN>
+// LDSA: `atlas` points to the workgroup's LDS copy of the padded atlas (LDS reads).
+template <typename TexT, bool PIN, bool LDSA = false>
 __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restrict__ atlas,
                                              int tex, int Wp, double U, double V, bool in,
                                              int zcell)
@@ -166,24 +167,36 @@ __device__ __forceinline__ void request_cell(Cell<TexT> &c, const TexT *__restri
     const unsigned at = in ? (unsigned)tex + __umul24((unsigned)(int)V, (unsigned)Wp) +
                                  (unsigned)(int)U
                            : (unsigned)zcell;
+    const unsigned b0 = at * (unsigned)sizeof(TexT);
+    // the row below as a 64-bit offset: the compiler adds the pitch to the scalar base, and
+    // both loads take the same per-lane offset b0
+    const size_t b1 = (size_t)b0 + (size_t)Wp * sizeof(TexT);
+    auto load = [&](auto *t0, auto *t1) {
+        if constexpr (is_f16<TexT>) {  // merged by the compiler into one dword load per row
+            c.A = half2v{t0[0], t0[1]};
+            c.B = half2v{t1[0], t1[1]};
+        } else {
+            c.p00 = t0[0];
+            c.p01 = t0[1];
+            c.p10 = t1[0];
+            c.p11 = t1[1];
+        }
+    };
     // The atlas is a read-only kernel argument, so the compiler takes loads from it as
     // movable anywhere; seen through this (empty) statement the base is an ordinary pointer,
     // and the loads stay ahead of the statement at the end.
-    using GChar = const __attribute__((address_space(1))) char;
-    using GTex = const __attribute__((address_space(1))) TexT;
-    GChar *base = (GChar *)atlas;
-    if constexpr (PIN) asm volatile("" : "+s"(base));
-    const unsigned b0 = at * (unsigned)sizeof(TexT);
-    GTex *t0 = (GTex *)(base + b0);
-    GTex *t1 = (GTex *)(base + (b0 + (unsigned)Wp * sizeof(TexT)));
-    if constexpr (is_f16<TexT>) {  // merged by the compiler into one dword load per row
-        c.A = half2v{t0[0], t0[1]};
-        c.B = half2v{t1[0], t1[1]};
+    if constexpr (LDSA) {
+        using LChar = const __attribute__((address_space(3))) char;
+        using LTex = const __attribute__((address_space(3))) TexT;
+        LChar *base = (LChar *)atlas;
+        if constexpr (PIN) asm volatile("" : "+s"(base));
+        load((LTex *)(base + b0), (LTex *)(base + b1));
     } else {
-        c.p00 = t0[0];
-        c.p01 = t0[1];
-        c.p10 = t1[0];
-        c.p11 = t1[1];
+        using GChar = const __attribute__((address_space(1))) char;
+        using GTex = const __attribute__((address_space(1))) TexT;
+        GChar *base = (GChar *)atlas;
+        if constexpr (PIN) asm volatile("" : "+s"(base));
+        load((GTex *)(base + b0), (GTex *)(base + b1));
     }
     // no instruction and no wait: only an ordering point for the compiler
     if constexpr (PIN) asm volatile("" ::: "memory");
@@ -368,7 +381,27 @@ __device__ __forceinline__ float wave_sum(float y)
 //                      processed. This hides the texel latency where few waves share a SIMD
 //                      (small canvases); where the SIMDs are full of waves, they hide it, and
 //                      the second cell's instructions and registers only cost.
-enum { LAUNCH_TILE = 0, LAUNCH_PERSISTENT = 1, LAUNCH_TILE_PIPE = 2 };
+//   LAUNCH_TILE_PIPE_LDS  the pipelined build reading its texels from a copy of the padded atlas
+//                      that every workgroup stages in LDS first (small atlases, on request:
+//                      dbmp_set_atlas_placement).
+enum { LAUNCH_TILE = 0, LAUNCH_PERSISTENT = 1, LAUNCH_TILE_PIPE = 2, LAUNCH_TILE_PIPE_LDS = 3 };
+
+// The LDS copy of the padded atlas (LAUNCH_TILE_PIPE_LDS): `bytes` of it, copied by the whole
+// workgroup with 4-byte loads (element sizes are 2 or 4 bytes; an odd trailing 2-byte element
+// is copied alone), then a barrier. Returns the copy's base.
+template <typename TexT>
+__device__ __forceinline__ const TexT *stage_atlas(const TexT *__restrict__ atlas, int bytes)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t s_atlas[];
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(atlas);
+    const int words = bytes >> 2;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) s_atlas[i] = src[i];
+    if ((bytes & 3) && threadIdx.x == 0)
+        reinterpret_cast<uint16_t *>(s_atlas)[2 * words] =
+            reinterpret_cast<const uint16_t *>(atlas)[2 * words];
+    __syncthreads();
+    return reinterpret_cast<const TexT *>(s_atlas);
+}
 
 template <bool PERSIST, typename Body>
 __device__ __forceinline__ void run_schedule(int sched, int grab, const int *__restrict__ order,
@@ -428,7 +461,8 @@ struct Stored {
 // tile's squared error written to loss_tile.
 // The backward's walk over a tile's sorted list (defined below, after the forward kernel that
 // also runs it in the fused fit step).
-template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, int SV, typename IdAt>
+template <int NT, typename TexT, bool HAS_GA, bool PIPE, bool LDSA, int TS, int SV,
+          typename IdAt>
 __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          const Stored<SV, TexT> &st,
                                          PrimRec *__restrict__ s_rec,
@@ -446,24 +480,25 @@ __global__ void __launch_bounds__(TS * TS)
 k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list_cap,
              int *__restrict__ tile_count, int *__restrict__ tile_len, int *__restrict__ list_max,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
-             const TexT *__restrict__ atlas, int Wp, int zcell, const float *__restrict__ bg,
+             const TexT *__restrict__ atlas_g, int Wp, int zcell, const float *__restrict__ bg,
              float *__restrict__ image, float *__restrict__ alpha, int *__restrict__ saveK,
              float *__restrict__ saveT, const int *__restrict__ flags,
              unsigned long long *__restrict__ pair_counter, int sched, int grab,
              const int *__restrict__ order, int *__restrict__ queue,
              const float *__restrict__ target, float *__restrict__ loss_tile,
              float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
-             int *__restrict__ fit_state)
+             int *__restrict__ fit_state, int atl_bytes)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
-    constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT, PIPE = LAUNCH == LAUNCH_TILE_PIPE;
+    constexpr bool LDSA = LAUNCH == LAUNCH_TILE_PIPE_LDS;
+    constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT;
+    constexpr bool PIPE = LAUNCH == LAUNCH_TILE_PIPE || LDSA;
     // the fused step keeps its first visits' bilinear values for the backward (the pipelined
     // build runs where the grid leaves SIMDs with few waves, so registers are not its limit)
     constexpr int SVN = LAUNCH == LAUNCH_TILE
                             ? (is_f16<TexT> ? STORED_VISITS_F16 : STORED_VISITS)
-                        : LAUNCH == LAUNCH_TILE_PIPE
-                            ? (is_f16<TexT> ? STORED_VISITS_PIPE_F16 : STORED_VISITS_PIPE)
-                            : 0;
+                        : PIPE ? (is_f16<TexT> ? STORED_VISITS_PIPE_F16 : STORED_VISITS_PIPE)
+                               : 0;
     constexpr bool STORE = FUSED && SVN > 0;
     constexpr int SV = STORE ? SVN : 1;
     // A fit step's Adam state {updates applied, unused, gradient pending, unused}: this step's
@@ -482,6 +517,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         for (int i = threadIdx.x; i < BATCH * 8; i += NT) s_grad[i] = 0.f;
         __syncthreads();
     }
+    const TexT *atlas = atlas_g;
+    if constexpr (LDSA) atlas = stage_atlas<TexT>(atlas_g, atl_bytes);
     auto tile_body = [&](const int tile) {
         const int n = tile_count[tile];
         __syncthreads();  // every lane has read the count before it is re-armed
@@ -566,8 +603,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         auto find_req = [&](uint64_t &hits, Cell<TexT> &c, uint64_t &m) {
             double U = 0.0, V = 0.0;
             const int e = find(hits, U, V, m);
-            request_cell<TexT, true>(c, atlas, e >= 0 ? s_rec[e].tex : 0, Wp, U, V,
-                                     __builtin_amdgcn_inverse_ballot_w64(m), zcell);
+            request_cell<TexT, true, LDSA>(c, atlas, e >= 0 ? s_rec[e].tex : 0, Wp, U, V,
+                                           __builtin_amdgcn_inverse_ballot_w64(m), zcell);
             return e;
         };
         // The pipelined walk composites on every lane (no branch, so the wait for a cell's
@@ -647,7 +684,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                 if (e < 0) break;
                                 const PrimRec &r = s_rec[e];
                                 Cell<TexT> c;
-                                request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V,
+                                request_cell<TexT, false, LDSA>(c, atlas, r.tex, Wp, U, V,
                                                           __builtin_amdgcn_inverse_ballot_w64(m),
                                                           zcell);
                                 const Bil<TexT> b = blend<TexT>(c);
@@ -670,7 +707,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                         npairs += __popcll(m);
                         if (__builtin_amdgcn_inverse_ballot_w64(m)) {  // the support lanes only
                             Cell<TexT> c;
-                            request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V, true, zcell);
+                            request_cell<TexT, false, LDSA>(c, atlas, r.tex, Wp, U, V, true,
+                                                            zcell);
                             const float a = r.ka * blend<TexT>(c).m();  // Eq. (3)
                             if (T >= DBMP_TAU) { K = b0 + e; TK = T; }
                             const float w = T * a;
@@ -725,7 +763,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
         const int lane = threadIdx.x & 63;
         const bool staged = n <= BATCH;  // the forward's only batch is still in s_rec
         if (in_lds)
-            bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return s_ids[j]; }, staged, st, s_rec,
+            bwd_walk<NT, TexT, false, PIPE, LDSA>(n, [&](int j) { return s_ids[j]; }, staged, st, s_rec,
                                             s_grad,
                                       recs,
                                       atlas, Wp, zcell, tg, vmask, g0, g1, g2, 0.f, b0, b1,
@@ -733,7 +771,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                       tg.valid ? K : -1, TK, dparams, cu1, cv1, cu_cv, cv_cu,
                                       lane);
         else
-            bwd_walk<NT, TexT, false, PIPE>(n, [&](int j) { return ((volatile int *)seg)[j]; },
+            bwd_walk<NT, TexT, false, PIPE, LDSA>(n, [&](int j) { return ((volatile int *)seg)[j]; },
                                       staged, Stored<1, TexT>(), s_rec, s_grad, recs, atlas, Wp, zcell, tg, vmask,
                                       g0,
                                       g1, g2,
@@ -774,7 +812,8 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
 // conversion): summing the uncentred coordinates and subtracting cu1 s0 + cv1 s1 at the flush
 // instead saves two instructions but cancels, and it was measured to lose about two decimal
 // digits on the angle's gradient.
-template <int NT, typename TexT, bool HAS_GA, bool PIPE, int TS, int SV, typename IdAt>
+template <int NT, typename TexT, bool HAS_GA, bool PIPE, bool LDSA, int TS, int SV,
+          typename IdAt>
 __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          const Stored<SV, TexT> &st,
                                          PrimRec *__restrict__ s_rec,
@@ -809,8 +848,8 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             msk = support_mask(r, U, V, vmask);
             if (msk != 0) { e = k; break; }
         }
-        request_cell<TexT, true>(c, atlas, e >= 0 ? s_rec[e].tex : 0, Wp, U, V,
-                                 __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
+        request_cell<TexT, true, LDSA>(c, atlas, e >= 0 ? s_rec[e].tex : 0, Wp, U, V,
+                                       __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
         Uc = (float)(U - cu1);
         Vc = (float)(V - cv1);
         return e;
@@ -897,8 +936,8 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                 const uint64_t msk = support_mask(r, U, V, vmask);
                 if (msk == 0) continue;
                 Cell<TexT> c;
-                request_cell<TexT, false>(c, atlas, r.tex, Wp, U, V,
-                                          __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
+                request_cell<TexT, false, LDSA>(c, atlas, r.tex, Wp, U, V,
+                                                __builtin_amdgcn_inverse_ballot_w64(msk), zcell);
                 under(e, b0 + e, c, (float)(U - cu1), (float)(V - cv1));
             }
         }
@@ -941,20 +980,24 @@ __global__ void __launch_bounds__(TS * TS)
 k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, int list_cap,
              const int *__restrict__ tile_len,
              const ImgDev *__restrict__ imgs, int n_images, int n_tiles,
-             const TexT *__restrict__ atlas, int Wp, int zcell, const float *__restrict__ bg,
+             const TexT *__restrict__ atlas_g, int Wp, int zcell, const float *__restrict__ bg,
              const int *__restrict__ saveK, const float *__restrict__ saveT,
              const float *__restrict__ gI, const float *__restrict__ target,
              float *__restrict__ loss_tile, const float *__restrict__ gA,
              float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
              const int *__restrict__ flags, int sched, int grab,
-             const int *__restrict__ order, int *__restrict__ queue)
+             const int *__restrict__ order, int *__restrict__ queue, int atl_bytes)
 {
-    constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT, PIPE = LAUNCH == LAUNCH_TILE_PIPE;
+    constexpr bool LDSA = LAUNCH == LAUNCH_TILE_PIPE_LDS;
+    constexpr bool PERSIST = LAUNCH == LAUNCH_PERSISTENT;
+    constexpr bool PIPE = LAUNCH == LAUNCH_TILE_PIPE || LDSA;
     __shared__ PrimRec s_rec[BATCH];
     __shared__ float s_loss[TS * TS / 64];
     __shared__ float s_grad[BATCH * 8];  // per-entry partial sums of the gradient
     for (int i = threadIdx.x; i < BATCH * 8; i += TS * TS) s_grad[i] = 0.f;
     __syncthreads();
+    const TexT *atlas = atlas_g;
+    if constexpr (LDSA) atlas = stage_atlas<TexT>(atlas_g, atl_bytes);
     auto tile_body = [&](const int tile) {
         const int n = tile_len[tile];
         if (n > list_cap) return;  // the forward did not render this tile
@@ -989,7 +1032,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
             TK = saveT[gp];
         }
         const int *seg = lists + (size_t)tile * list_cap;
-        bwd_walk<TS * TS, TexT, HAS_GA, PIPE>(n, [&](int j) { return seg[j]; }, false,
+        bwd_walk<TS * TS, TexT, HAS_GA, PIPE, LDSA>(n, [&](int j) { return seg[j]; }, false,
                                               Stored<1, TexT>(), s_rec,
                                               s_grad,
                                         recs,
@@ -1024,13 +1067,13 @@ static inline bool pipelined(const RasterArgs &a)
 // Launches `kern`; with timing events armed, through hipExtLaunchKernel, which has the device
 // record them when the kernel starts and when it ends.
 template <typename K, typename... Args>
-static void launch_kernel(K kern, int grid, int block, hipStream_t st, hipEvent_t e0,
-                          hipEvent_t e1, Args... args)
+static void launch_kernel(K kern, int grid, int block, size_t lds, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1, Args... args)
 {
     if (e0 && e1)
-        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, e0, e1, 0, args...);
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, e0, e1, 0, args...);
     else
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, args...);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, args...);
 }
 
 // Workgroups of a kernel that one compute unit holds at once (registers and LDS permitting).
@@ -1060,14 +1103,15 @@ static void fwd_t(const RasterArgs &a, hipStream_t st)
     const int grid = LAUNCH == LAUNCH_PERSISTENT
                          ? persistent_grid(k_raster_fwd<TS, TexT, BGPP, FUSED, LAUNCH>, TS * TS, a)
                          : a.n_tiles;
-    launch_kernel(k_raster_fwd<TS, TexT, BGPP, FUSED, LAUNCH>, grid, TS * TS, st, a.ev_start,
-        a.ev_stop, a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len,
+    const int atl = LAUNCH == LAUNCH_TILE_PIPE_LDS ? a.atlas_lds_bytes : 0;
+    launch_kernel(k_raster_fwd<TS, TexT, BGPP, FUSED, LAUNCH>, grid, TS * TS,
+        (size_t)((atl + 15) & ~15), st, a.ev_start, a.ev_stop, a.recs, const_cast<int *>(a.lists), a.list_cap, a.tile_count, a.tile_len,
         a.list_max, a.imgs,
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.zcell, a.bg, a.image, a.alpha,
         a.saveK,
         a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue, a.target,
         a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu),
-        a.fit_state);
+        a.fit_state, atl);
 }
 
 template <int TS, typename TexT, bool BGPP, bool GA, bool MSE, int LAUNCH>
@@ -1077,12 +1121,13 @@ static void bwd_t(const RasterArgs &a, hipStream_t st)
     const int grid = LAUNCH == LAUNCH_PERSISTENT
                          ? persistent_grid(k_raster_bwd<TS, TexT, BGPP, GA, MSE, LAUNCH>, TS * TS, a)
                          : a.n_tiles;
-    launch_kernel(k_raster_bwd<TS, TexT, BGPP, GA, MSE, LAUNCH>, grid, TS * TS, st, a.ev_start,
-        a.ev_stop, a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
+    const int atl = LAUNCH == LAUNCH_TILE_PIPE_LDS ? a.atlas_lds_bytes : 0;
+    launch_kernel(k_raster_bwd<TS, TexT, BGPP, GA, MSE, LAUNCH>, grid, TS * TS,
+        (size_t)((atl + 15) & ~15), st, a.ev_start, a.ev_stop, a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
         (const TexT *)a.atlas_pad, a.Wp, a.zcell, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI,
         a.target,
         a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
-        (float)(cv / cu), a.flags, a.sched, a.grab, a.order, a.queue + 2);
+        (float)(cv / cu), a.flags, a.sched, a.grab, a.order, a.queue + 2, atl);
 }
 
 template <int TS, typename TexT, int LAUNCH>

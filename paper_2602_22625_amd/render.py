@@ -125,6 +125,11 @@ class Renderer:
         it."""
         capi.dbmp_set_schedule(self.ctx, schedule, workgroups_per_cu, items_per_grab)
 
+    def set_atlas_placement(self, placement):
+        """Where the raster kernels read texels (capi.DBMP_ATLAS_GLOBAL or DBMP_ATLAS_LDS);
+        results do not depend on it."""
+        capi.dbmp_set_atlas_placement(self.ctx, placement)
+
     # -- atlas -------------------------------------------------------------------------------
     def set_atlas(self, atlas):
         """Pads and stores the bitmaps once; later renders may pass atlas=None."""

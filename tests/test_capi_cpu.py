@@ -97,6 +97,7 @@ def test_host_argument_checks_need_no_device():
     assert lib.dbmp_mse_loss(None, None, None) == capi.DBMP_EINVAL
     assert lib.dbmp_longest_list(None, None) == -1
     assert lib.dbmp_set_schedule(None, 1, 4, 1) == capi.DBMP_EINVAL
+    assert lib.dbmp_set_atlas_placement(None, 1) == capi.DBMP_EINVAL
     assert lib.dbmp_fit_step(None, None, None, None, 0, 4, 4, None, 0, 1.0, 16, None, None,
                              None, None, None, None, 1e-2, 0.9, 0.999, 1e-8) == capi.DBMP_EINVAL
     assert lib.dbmp_fit_step_batched(None, None, 1, None, None, None, None, 1.0, 16, None, None,

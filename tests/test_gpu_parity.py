@@ -103,7 +103,7 @@ def test_images_bitwise_identical_across_tile_sizes(R):
     d = synth.make_workload("c1")
     p, idx, a = to_dev(d)
     outs = []
-    for tile in (8, 16, 32):
+    for tile in (8, 16, 32, 0):  # 0: the library's choice
         img, alp, _ = gpu_render(R, p, idx, a, 512, 512, (1, 1, 1), tile=tile)
         outs.append((img.cpu().numpy().copy(), alp.cpu().numpy().copy()))
     for o in outs[1:]:
@@ -563,6 +563,56 @@ def test_autograd_function_matches_oracle(R):
     gA = np.full((128, 128), 0.5 / (128 * 128))
     gref = oracle.render_backward(d["params"], d["idx"], d["atlas"], 128, 128, gI, gA)
     assert_grads(p.grad.cpu().numpy(), gref)
+
+
+def _one_bitmap_c1():
+    """The 512 x 512 / 4,096-primitive workload drawing every primitive from one 64 x 64 bitmap
+    (a padded atlas of 17.9 KB in float32, 9.0 KB in float16)."""
+    d = synth.make_workload("c1")
+    return d["params"], np.zeros_like(d["idx"]), d["atlas"][:1].copy(), d["target"]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_atlas_in_lds_equals_global(dtype):
+    """dbmp_set_atlas_placement(DBMP_ATLAS_LDS): launches of the pipelined build stage the padded
+    atlas in LDS and sample it there. Against the default placement on the same inputs: images
+    and alpha bitwise equal, gradients (dL/dI and dL/dA) and fused-step gradients within 1e-5
+    of each column's scale; at 128^2 (the 64-primitive workload) and on the 512^2 canvas with
+    one bitmap; and with the full 16-bitmap atlas (279 KB: too large, so the launch reads
+    device memory) also bitwise."""
+    from paper_2602_22625_amd import capi
+    from paper_2602_22625_amd.render import Renderer
+    dev = torch.device("cuda")
+    d0 = synth.make_workload("c0")
+    d1 = synth.make_workload("c1")
+    cases = [(128, d0["params"], d0["idx"], d0["atlas"], d0["target"]),
+             (512,) + _one_bitmap_c1(),
+             (512, d1["params"], d1["idx"], d1["atlas"], d1["target"])]
+    for S, params, idx, atlas, target in cases:
+        p = torch.tensor(params, device=dev)
+        i_t = torch.tensor(idx, device=dev)
+        a = torch.tensor(atlas, device=dev)
+        if dtype == "f16":
+            a = a.to(torch.float16)
+        t = torch.tensor(target, device=dev)
+        bg = torch.ones(3, device=dev)
+        rng = np.random.default_rng(S)
+        gI = torch.tensor(rng.standard_normal((3, S, S)), dtype=torch.float32, device=dev)
+        gA = torch.tensor(rng.standard_normal((S, S)), dtype=torch.float32, device=dev)
+        outs = []
+        for place in (capi.DBMP_ATLAS_GLOBAL, capi.DBMP_ATLAS_LDS):
+            R = Renderer()
+            R.set_atlas_placement(place)
+            img, alp = R.render(p, i_t, a, S, S, bg, 1.0, 16)
+            g = R.backward(gI, gA, n_params=params.shape[0])
+            f, gf = R.render_mse(p, i_t, a, S, S, t, bg, 1.0, 16)
+            R.check()
+            outs.append([x.cpu().numpy().copy() for x in (img, alp, g, f, gf)])
+        (i0, a0, g0, f0, h0), (i1, a1, g1, f1, h1) = outs
+        assert np.array_equal(i0, i1) and np.array_equal(a0, a1) and np.array_equal(f0, f1), S
+        for x0, x1 in ((g0, g1), (h0, h1)):
+            scale = np.abs(x0).max(axis=0) + 1e-30
+            assert np.all(np.abs(x0.astype(np.float64) - x1) <= 1e-5 * scale), S
 
 
 def test_stored_atlas_equals_per_call_atlas():
