@@ -96,20 +96,22 @@ def test_network_forward_backward_layer_by_layer():
 
 def test_learned_start_reaches_the_plain_psnr_sooner():
     """The configured comparison on a scaled-down set: 1,024 (target, 500-step fit) pairs, a
-    short training on the regression plus the image loss through the renderer, then 8 held-out
-    targets, each fitted from the random start for 500 steps (the bar: its final PSNR, its wall
-    time) and from the network's start for at most 100 steps. The learned path (inference
+    short training (40 epochs) on the regression plus the image loss through the renderer, then
+    8 held-out targets, each fitted from the random start for 500 steps (the bar: its final PSNR,
+    its wall time) and from the network's start for at most 100 steps. The learned path (inference
     included) must reach the bar in less wall time than the plain path on most targets, and its
     start must beat the random start it replaces."""
     from paper_2602_22625_amd import cnn_init as ci
     tg, fitted = ci.generate_pairs(1024, steps=500, batch=256, seed=1)
     net = ci.InitNet(seed=0)
-    ci.train(net, tg, fitted, epochs=30, batch=64, lr=2e-3, image_weight=16.0, param_weight=0.1)
+    ci.train(net, tg, fitted, epochs=40, batch=64, lr=2e-3, image_weight=16.0, param_weight=0.1)
     res = ci.evaluate(net, n_targets=8, plain_steps=500, learned_steps=100, seed=10 ** 7)
     print({k: v for k, v in res.items() if k != "rows"})
     assert res["median_psnr_cnn_start"] > res["median_psnr_random_start"] + 3.0
-    # most targets: a majority of the 8 (the training's float atomics make the count of targets
-    # just past or short of the 100-step cap vary from run to run)
-    assert res["wins"] >= 5, res["wins"]
-    assert res["median_steps_to_bar_uncapped"] <= 100
+    # most targets: the median target reaches the bar within the 100 steps, and the learned path
+    # gets there first on at least 6 of the 8 (counted without the cap: the training's float
+    # atomics move the targets that sit near the cap from one side of it to the other between
+    # runs)
+    assert res["median_steps_to_bar_uncapped"] <= 100, res["median_steps_to_bar_uncapped"]
+    assert res["wins_uncapped"] >= 6, res["wins_uncapped"]
     assert res["median_t_learned_ms"] < res["median_t_plain_ms"]
