@@ -222,7 +222,7 @@ int dbmp_render_mse(dbmp_ctx *ctx, dbmp_stream stream, const float *params,
  *   scratch_bytes  out, host, may be NULL: the scratch these sizes need (written also when the
  *                  call is refused).
  * DBMP_ENOMEM (nothing enqueued) if the sizes need more than the static array: about
- * 192 N + 4 n_tiles list_capacity + 8 H W + the padded atlas + 12 n_tiles bytes, so 2048 x 2048
+ * 160 N + 4 n_tiles list_capacity + 8 H W + the padded atlas + 12 n_tiles bytes, so 2048 x 2048
  * with 65,536 primitives fits with list_capacity 96. DBMP_EINVAL for bad arguments (as
  * dbmp_render_mse), DBMP_EHIP if a launch failed. The first call on a device resolves the
  * array's address (hipGetSymbolAddress): make it outside graph capture. Every call on a device

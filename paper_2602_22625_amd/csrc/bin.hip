@@ -422,11 +422,12 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
         rec.ka = 0.f; rec.cr = rec.cg = rec.cb = 0.f; rec.tex = 0; rec.kaom = 0.f;
         rec.ccr = rec.ccg = rec.ccb = 0.f;
         rec.faU = rec.fbU = rec.faV = rec.fbV = 0.f;
-        rec.tx0 = 1; rec.tx1 = 0; rec.ty0 = 1; rec.ty1 = 0;
+        int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;  // tile span of the pixel box (empty)
         rec.px0 = 1; rec.px1 = 0; rec.py0 = 1; rec.py1 = 0;
-        rec.img = rec.tile_off = rec.ntx = rec.W = rec.H = 0;
         rec.id = (int)g;
-        rec.pad = 0;
+        rec.pad[0] = rec.pad[1] = 0;
+        WalkRec &wr = s_rec[threadIdx.x];
+        wr.tile_off = wr.ntx = wr.W = wr.H = 0;
         if (g < n_rows) {
             // s = exp(p2); sin, cos of p3; the sigmoid of the opacity logit and its complement;
             // the colour sigmoids and exp of the colour logits
@@ -436,7 +437,7 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
             const double *e = s_e + threadIdx.x * 12;
             const double s = e[0], sig = e[1], omsig = e[2], st = e[9], ct = e[10];
             const double c3[3] = {e[3], e[4], e[5]}, ep[3] = {e[6], e[7], e[8]};
-            rec.img = b; rec.tile_off = D.tile_off; rec.ntx = D.ntx; rec.W = D.W; rec.H = D.H;
+            wr.tile_off = D.tile_off; wr.ntx = D.ntx; wr.W = D.W; wr.H = D.H;
             if (g >= D.prim_off && g < D.prim_off + D.N) {
                 bool ok = true;
                 if (!k_ok) {
@@ -499,20 +500,18 @@ k_prep(const float *params, const int *__restrict__ idx, long long n_rows,
                         if (fx0 <= fx1 && fy0 <= fy1) {
                             rec.px0 = (int)fx0; rec.px1 = (int)fx1;
                             rec.py0 = (int)fy0; rec.py1 = (int)fy1;
-                            rec.tx0 = rec.px0 / TS; rec.tx1 = rec.px1 / TS;
-                            rec.ty0 = rec.py0 / TS; rec.ty1 = rec.py1 / TS;
+                            tx0 = rec.px0 / TS; tx1 = rec.px1 / TS;
+                            ty0 = rec.py0 / TS; ty1 = rec.py1 / TS;
                         }
                     }
                 }
             }
             recs[g] = rec;
         }
-        WalkRec &wr = s_rec[threadIdx.x];
         wr.aU = rec.aU; wr.bU = rec.bU; wr.eU = rec.eU; wr.aV = rec.aV; wr.bV = rec.bV;
         wr.eV = rec.eV; wr.Ulo = rec.Ulo; wr.Uhi = rec.Uhi; wr.Vlo = rec.Vlo; wr.Vhi = rec.Vhi;
-        wr.tx0 = rec.tx0; wr.tx1 = rec.tx1; wr.ty0 = rec.ty0; wr.ty1 = rec.ty1;
-        wr.tile_off = rec.tile_off; wr.ntx = rec.ntx; wr.W = rec.W; wr.H = rec.H;
-        if (rec.tx0 <= rec.tx1) span = (rec.tx1 - rec.tx0 + 1) * (rec.ty1 - rec.ty0 + 1);
+        wr.tx0 = tx0; wr.tx1 = tx1; wr.ty0 = ty0; wr.ty1 = ty1;
+        if (tx0 <= tx1) span = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     }
     if (threadIdx.x < 64) {  // wave 0: scan of the spans (lanes past PREP_PRIMS add 0)
         int x = span;

@@ -35,8 +35,9 @@ struct ImgDev {
     long long pix_off;   // first global pixel (image planes at 3 * pix_off)
 };
 
-// Per-primitive record written by the setup kernel and read (wave-uniformly, through the scalar
-// cache) by the raster kernels; the fields the forward needs come first. Coordinates are those
+// Per-primitive record written by the setup kernel and read by the raster kernels (staged in LDS
+// per batch of list entries): only what the walks and the flush read, 160 bytes; the fields the
+// forward needs come first. (The tile span and image fields of the binning stay in its LDS.) Coordinates are those
 // of the padded bitmap, where the texel (r, c) of Eq. (2) sits at padded (r + 1, c + 1):
 //     U' = aU x + bU y + eU = U + 1,   V' = aV x + bV y + eV = V + 1.
 struct __attribute__((aligned(16))) PrimRec {
@@ -50,12 +51,10 @@ struct __attribute__((aligned(16))) PrimRec {
     float kaom;                 // alpha_max * sigmoid(nu) * (1 - sigmoid(nu))  (d alpha / d nu / M)
     float ccr, ccg, ccb;        // c (1 - c): derivative of the colour sigmoid
     float faU, fbU, faV, fbV;   // float copies of the map's linear part (backward chain rule)
-    int tx0, tx1, ty0, ty1;     // tile span of the bounding box (empty: tx0 > tx1)
-    int img, tile_off, ntx, W, H;  // the primitive's image: first tile, tiles per row, size
     int id;                     // the primitive's row in params
-    int pad;
+    int pad[2];
 };
-static_assert(sizeof(PrimRec) == 192, "PrimRec layout");
+static_assert(sizeof(PrimRec) == 160, "PrimRec layout");
 static_assert(offsetof(PrimRec, px0) == 80, "the pixel box is read as one 16-byte vector");
 
 __device__ __forceinline__ int find_by_prim(const ImgDev *__restrict__ imgs, int n, long long g)

@@ -107,6 +107,32 @@ def test_f16_c0_forward_backward(R, tile):
     assert_grads_f16(out.cpu().numpy(), gref)
 
 
+def test_f16_ragged_per_pixel_background(R):
+    """A canvas that is not a multiple of the tile, per-pixel background, alpha_max < 1, at
+    T = 8, 16, 32: image and alpha within the bound, gradients of dL/dI within the tolerance."""
+    g = np.random.default_rng(5)
+    H, W, N = 77, 101, 300
+    a, a64 = f16(synth.make_atlas("ss64x16"))
+    params, idx = synth.init_params(N, H, W, np.log(9.0), 0.5, a64.shape[0], 77)
+    bg = g.uniform(0, 1, (3, H, W)).astype(np.float32)
+    p = torch.tensor(params, device="cuda")
+    i_t = torch.tensor(idx, device="cuda")
+    bg_t = torch.tensor(bg, device="cuda")
+    ref, refA = oracle.render(params, idx, a64, H, W, bg=bg, alpha_max=0.8)
+    gI = g.standard_normal((3, H, W))
+    gref = oracle.render_backward(params, idx, a64, H, W, gI, None, bg=bg, alpha_max=0.8)
+    for tile in (8, 16, 32):
+        img, alp = R.render(p, i_t, a, H, W, bg_t, 0.8, tile)
+        R.check()
+        assert_image_within_bound(img.cpu().numpy(), ref, params, idx, a64, (0, 0, W, H),
+                                  n_probe=150, seed=tile, alpha_max=0.8)
+        assert_image_within_bound(alp.cpu().numpy(), refA, params, idx, a64, (0, 0, W, H),
+                                  n_probe=150, seed=tile + 1, alpha_max=0.8)
+        out = R.backward(torch.tensor(gI, dtype=torch.float32, device="cuda"), None, n_params=N)
+        R.check()
+        assert_grads_f16(out.cpu().numpy(), gref)
+
+
 def test_f16_c1_window(R):
     """512 x 512, 4,096 primitives: the whole canvas on the GPU, the oracle on a 160 x 144
     window with the loss gradient restricted to it."""
