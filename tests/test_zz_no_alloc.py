@@ -19,7 +19,9 @@ def _inputs(name, bf16=False):
     dev = "cuda"
     p = torch.tensor(d["params"], device=dev)
     idx = torch.tensor(d["idx"], device=dev)
-    if bf16:
+    if bf16 == "f16":  # the reduced-precision raster
+        a = torch.tensor(d["atlas"].astype(np.float16), device=dev)
+    elif bf16:
         a = torch.tensor(synth.f32_to_bf16_bits(d["atlas"]).view(np.int16),
                          device=dev).view(torch.bfloat16)
     else:
@@ -31,7 +33,8 @@ def _inputs(name, bf16=False):
 def _noalloc(H, W, p, idx, a, t, tile, cap, accumulate=0, grad=None):
     N = p.shape[0]
     B, Hb, Wb = a.shape
-    code = capi.DBMP_BF16 if a.dtype == torch.bfloat16 else capi.DBMP_F32
+    code = {torch.bfloat16: capi.DBMP_BF16, torch.float16: capi.DBMP_F16}.get(a.dtype,
+                                                                            capi.DBMP_F32)
     bg = torch.ones(3, device="cuda")
     img = torch.empty(3, H, W, device="cuda")
     g = grad if grad is not None else torch.empty(N, 8, device="cuda")
@@ -62,10 +65,12 @@ def _assert_same(img_n, g_n, img_c, g_c):
 
 
 def test_noalloc_matches_render_mse_on_two_calls_second_smaller():
-    cases = [("c1", 16, False), ("c0", 8, True)]  # 512x512 / 4,096 fp32, then 128x128 / 64 bf16
+    # 512x512 / 4,096 fp32, then 128x128 / 64 bf16, then 128x128 fp16 (each call smaller than
+    # the first)
+    cases = [("c1", 16, False), ("c0", 8, True), ("c0", 16, "f16")]
     for name, tile, bf16 in cases:
         H, W, p, idx, a, t = _inputs(name, bf16)
-        print("noalloc case", name, tile, "bf16" if bf16 else "fp32", flush=True)
+        print("noalloc case", name, tile, a.dtype, flush=True)
         img_n, g_n, status, used = _noalloc(H, W, p, idx, a, t, tile, cap=256)
         assert np.all(status == 0), status
         assert 0 < used <= capi.DBMP_NOALLOC_SCRATCH_MB << 20
