@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--c4-pairs", type=int, default=10000)
     ap.add_argument("--c4-epochs", type=int, default=20)
     ap.add_argument("--cpu-window", type=int, default=192)
-    ap.add_argument("--profile", choices=["c0", "c1", "c2", "c4", "cnn"], default=None,
+    ap.add_argument("--profile", choices=["c0", "c1", "c2", "c2f16", "c4", "cnn"], default=None,
                     help="profiling driver: `--steps` held fit steps of this workload, then the "
                          "separate forward and backward as often, then one 256 MiB device copy "
                          "(the reference kernel that calibrates the HBM byte counters); with "
@@ -568,7 +568,11 @@ def bench_c4(args, torch):
 def profile_driver(args, synth, capi, Fitter, Renderer, np, torch, dev):
     """`--steps` fit steps at the benchmark's held state (eager, so each launch is a dispatch of
     its own), then as many separate forwards and MSE backwards, then a 256 MiB copy."""
-    wl, d, p0, idx, atlas, target = load_workload(args.profile, synth, np, torch, dev)
+    f16 = args.profile == "c2f16"  # the 2048^2 workload on the reduced-precision raster
+    wl, d, p0, idx, atlas, target = load_workload("c2" if f16 else args.profile, synth, np, torch,
+                                                  dev)
+    if f16:
+        atlas = torch.tensor(d["atlas"].astype(np.float16), device=dev)
     sched = capi.DBMP_SCHED_SORTED if args.profile == "c1" else capi.DBMP_SCHED_GRID
     fit = Fitter(p0, idx, atlas, target, tile=wl.tile, lr=1e-2)
     fit.set_launch(wl.tile, sched)
