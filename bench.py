@@ -14,7 +14,7 @@ number of steps does not move it. The value is primitive-pixel evaluations per s
 (pixel, primitive) pairs the timed steps evaluated (counted on the device, one popcount per
 wave and primitive; pinned in the tests against an exact host count) over the steps' wall time.
 
-Printed: one JSON line. --gpus N > 1 is refused: this build measures one GPU.
+Printed: one JSON line. --gpus N > 1 is refused: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -191,7 +191,7 @@ def main():
                          "prints nothing on stdout")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures a single GPU; multi-GPU runs are not part of this build",
+        print("bench.py measures a single GPU; runs on several GPUs are not supported",
               file=sys.stderr)
         sys.exit(2)
 
