@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-f16", action="store_true")
+    ap.add_argument("--no-aids", action="store_true")
     ap.add_argument("--c4-pairs", type=int, default=10000)
     ap.add_argument("--c4-epochs", type=int, default=20)
     ap.add_argument("--cpu-window", type=int, default=192)
@@ -313,6 +314,11 @@ def main():
     log("c2 separate: fwd %.3f ms bwd %.3f ms" % (f2 * 1e3, b2 * 1e3))
     del fit, R2
 
+    # ---------------- the steps either side of the fit, on the same canvas and primitives -------
+    if not args.no_aids:
+        extra["aids_and_export_2048sq"] = bench_aids(capi, wl, d, p0, idx, atlas, target, np,
+                                                     torch, dev)
+
     # ---------------- the reduced-precision raster (fp16 texels) on the same workload ----------
     if not args.no_f16:
         extra["f16_raster_2048sq"] = bench_f16(args, capi, metrics, Fitter, wl, d, p0, idx,
@@ -376,6 +382,80 @@ def main():
                       "evaluated pairs in %.2f s" % (w, w, sp, tc)}
         log("cpu baseline %.3e evals/s on %d threads" % (sp / tc, oracle.threads()))
     print(json.dumps(out), flush=True)
+
+
+def bench_aids(capi, wl, d, p0, idx, atlas, target, np, torch, dev):
+    """The kernels either side of the fit on the headline canvas and primitives, each timed with
+    HIP events over 20 calls, against the HBM bytes it must move at least (its inputs read and
+    outputs written once): the noise canvas and the spatial-constraint objective (per pixel),
+    re-initialisation of transparent primitives (per primitive), the Gaussian blur of the atlas,
+    structure-aware initialisation of all 65,536 primitives, and the layer export at export
+    scale 1 (every primitive's layer: its box of alpha values)."""
+    from paper_2602_22625_amd import aids
+    H, W, N = wl.H, wl.W, wl.N
+    HW = H * W
+    st = torch.cuda.current_stream()
+    sh = capi.stream_handle()
+
+    def timed(fn, reps=20):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    def row(t, nbytes, unit_note):
+        return {"us": round(t * 1e6, 2), "min_bytes": int(nbytes),
+                "GBps": round(nbytes / t * 1e-9, 1),
+                "hbm_frac": round(nbytes / t * 1e-9 / PEAK_HBM_GBS, 4), "bytes_are": unit_note}
+
+    out = {}
+    bg = torch.empty(3, H, W, device=dev)
+    t = timed(lambda: aids.dbmp_noise_canvas(sh, 1234, 7, H, W, bg))
+    out["noise_canvas"] = row(t, 12 * HW, "3 float32 written per pixel")
+    img = torch.rand(3, H, W, device=dev)
+    alp = torch.rand(H, W, device=dev)
+    ta = torch.rand(H, W, device=dev)
+    gI = torch.empty_like(img)
+    gA = torch.empty_like(alp)
+    loss = torch.zeros(1, device=dev)
+    t = timed(lambda: aids.dbmp_constraint_loss(sh, img, alp, target, ta, H, W, 0.5, gI, gA, loss))
+    out["constraint_loss"] = row(t, 48 * HW, "image, alpha, target, target alpha read; "
+                                             "dL/dI, dL/dA written (float32)")
+    params = p0.clone()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    prop = p0.clone()
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    t = timed(lambda: aids.dbmp_reinit_transparent(sh, params, m, v, prop, N, 0.05, cnt))
+    out["reinit_transparent"] = row(t, 7 * 32 * N, "parameters and both moments read and "
+                                                  "written, proposals read (32 B per row each)")
+    blurred = torch.empty_like(atlas)
+    B, Hb, Wb = atlas.shape
+    code = aids._atlas_code(atlas)
+    t = timed(lambda: aids.dbmp_blur_atlas(sh, atlas, B, Hb, Wb, code, 1.0, 3.0, blurred))
+    out["blur_atlas"] = row(t, 2 * atlas.numel() * atlas.element_size(),
+                            "the bf16 atlas read and its blurred copy written")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    draws = (torch.rand(N, device=dev, generator=gen), torch.rand(N, device=dev, generator=gen),
+             torch.randn(N, 3, device=dev, generator=gen))
+    t = timed(lambda: aids.sa_init(target, N, 4.0, 24.0, nu_init=-4.0, draws=draws), reps=5)
+    out["sa_init"] = row(t, 16 * HW + 32 * N, "target read, NLV written, parameters written "
+                                              "(the scan's workspace traffic not counted)")
+    boxes, offs, al, col = aids.export_layers(p0, idx, atlas, H, W, rho=1.0)
+    total = int(offs[N].item())
+    mw, mh = int(boxes[:, 2].max().item()), int(boxes[:, 3].max().item())
+    t = timed(lambda: aids.dbmp_export_layers(sh, p0, idx, N, atlas, B, Hb, Wb, code, H, W, 1.0,
+                                              1.0, boxes, offs, mw, mh, al, col))
+    out["export_layers_rho1"] = row(t, 4 * total + 12 * N,
+                                    "every layer's alpha box (%d values) and colours written"
+                                    % total)
+    log("aids at 2048^2: " + ", ".join("%s %.1f us" % (k, r["us"]) for k, r in out.items()))
+    return out
 
 
 def bench_f16(args, capi, metrics, Fitter, wl, d, p0, idx, target, k_bf16, extra, np, torch,

@@ -33,7 +33,7 @@ typedef void *dbmp_export_stream; /* hipStream_t */
  *            non-finite parameter row);
  *   offsets  out, device int64 [N + 1]: offsets[i] = sum of w h over the primitives before i,
  *            offsets[N] = the total (the alpha buffer's length for stage 2);
- *   max_wh   out, device int32 [2]: the largest w and the largest h (stage 2's grid).
+ *   max_wh   out, device int32 [2]: the largest w and the largest h.
  */
 int dbmp_export_boxes(dbmp_export_stream stream, const float *params, int N, int Hb, int Wb,
                       int H, int W, double rho, int32_t *boxes, long long *offsets,

@@ -8,6 +8,7 @@
 #include "diffbmp.h"
 
 #include <limits.h>
+#include <algorithm>
 #include <math.h>
 
 namespace dbmp {
@@ -88,17 +89,11 @@ __device__ __forceinline__ unsigned long long dbits(double x)
     return (unsigned long long)__double_as_longlong(x);
 }
 
-__global__ void k_lv_init(unsigned long long *minmax)
-{
-    minmax[0] = 0x7ff0000000000000ull;  // +inf
-    minmax[1] = 0ull;
-}
-
 // LV of a 16 x 16 pixel block: the (16 + 2h)^2 window of the three channels is staged in LDS;
 // each lane sums its pixel's window (only pixels inside the image) in float64.
 __global__ void __launch_bounds__(256)
 k_local_var(const float *__restrict__ img, int H, int W, int h, double *__restrict__ lv,
-            unsigned long long *__restrict__ minmax)
+            unsigned long long *__restrict__ bmm)
 {
     constexpr int S = LV_T + 2 * LV_HMAX;
     __shared__ float s[3][S][S];
@@ -132,16 +127,59 @@ k_local_var(const float *__restrict__ img, int H, int W, int h, double *__restri
         v = fmax(v / 3.0, 0.0);  // the one-pass form can round a zero variance below zero
         lv[(size_t)y * W + x] = v;
     }
-    // block min / max of the map (bit patterns of non-negative doubles), one atomic per wave
+    // the block's min / max of the map (bit patterns of non-negative doubles), written to its
+    // own slot (k_lv_minmax reduces the slots: no same-address atomics across the grid)
     unsigned long long lo = ok ? dbits(v) : 0x7ff0000000000000ull, hi = ok ? dbits(v) : 0ull;
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
         lo = a < lo ? a : lo;
         hi = b > hi ? b : hi;
     }
+    __shared__ unsigned long long s_lo[4], s_hi[4];
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(minmax, lo);
-        atomicMax(minmax + 1, hi);
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            lo = s_lo[w] < lo ? s_lo[w] : lo;
+            hi = s_hi[w] > hi ? s_hi[w] : hi;
+        }
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        bmm[2 * b] = lo;
+        bmm[2 * b + 1] = hi;
+    }
+}
+
+// The map's min / max from the blocks' slots: one workgroup.
+__global__ void __launch_bounds__(1024)
+k_lv_minmax(const unsigned long long *__restrict__ bmm, int nblocks,
+            unsigned long long *__restrict__ minmax)
+{
+    unsigned long long lo = 0x7ff0000000000000ull, hi = 0ull;
+    for (int b = threadIdx.x; b < nblocks; b += 1024) {
+        lo = bmm[2 * b] < lo ? bmm[2 * b] : lo;
+        hi = bmm[2 * b + 1] > hi ? bmm[2 * b + 1] : hi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    __shared__ unsigned long long s_lo[16], s_hi[16];
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) {
+            lo = s_lo[w] < lo ? s_lo[w] : lo;
+            hi = s_hi[w] > hi ? s_hi[w] : hi;
+        }
+        minmax[0] = lo;
+        minmax[1] = hi;
     }
 }
 
@@ -296,15 +334,20 @@ k_noise(unsigned long long seed, unsigned long long iter, long long npix,
 // ------------------------------------------------------------------------------------------
 // Spatial-constraint loss (Eq. 9) and re-initialisation (Supp. Sec. S1.4.2)
 // ------------------------------------------------------------------------------------------
+// A grid of at most CONSTRAINT_BLOCKS workgroups strides over the pixels; each workgroup adds
+// its share of the loss with one atomic (a wave-level atomic per 64 pixels on one address
+// serialised: 0.83 ms at 2048^2).
+constexpr int CONSTRAINT_BLOCKS = 2048;
+
 __global__ void __launch_bounds__(256)
 k_constraint(const float *__restrict__ I, const float *__restrict__ A,
              const float *__restrict__ t, const float *__restrict__ ta, long long npix,
              float lam, float *__restrict__ gI, float *__restrict__ gA, float *__restrict__ loss)
 {
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
     float acc = 0.f;
-    if (p < npix) {
-        const float inv3 = 1.f / (3.f * (float)npix), inv1 = 1.f / (float)npix;
+    const float inv3 = 1.f / (3.f * (float)npix), inv1 = 1.f / (float)npix;
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < npix;
+         p += (long long)gridDim.x * 256) {
         const bool m = ta[p] > 0.f;
         for (int c = 0; c < 3; ++c) {
             const float d = m ? I[c * npix + p] - t[c * npix + p] : 0.f;
@@ -317,7 +360,13 @@ k_constraint(const float *__restrict__ I, const float *__restrict__ A,
     }
     if (!loss) return;
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((threadIdx.x & 63) == 0 && acc != 0.f) atomicAdd(loss, acc);
+    __shared__ float s_acc[4];
+    if ((threadIdx.x & 63) == 0) s_acc[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float tot = s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3];
+        if (tot != 0.f) atomicAdd(loss, tot);
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -337,15 +386,17 @@ k_reinit(float *__restrict__ params, float *__restrict__ m, float *__restrict__ 
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SaLayout {
-    size_t minmax, lv, cdf, bsum, total;
+    size_t minmax, bmm, lv, cdf, bsum, total;
 };
 
-SaLayout sa_layout(long long npix)
+SaLayout sa_layout(long long npix, int H, int W)
 {
     SaLayout L;
     const long long nb = (npix + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const long long nblk = (long long)((W + LV_T - 1) / LV_T) * ((H + LV_T - 1) / LV_T);
     L.minmax = 0;
-    L.lv = up256(16);
+    L.bmm = up256(16);
+    L.lv = L.bmm + up256(16 * (size_t)nblk);
     L.cdf = L.lv + up256(8 * (size_t)npix);
     L.bsum = L.cdf + up256(8 * (size_t)npix);
     L.total = L.bsum + up256(8 * (size_t)nb);
@@ -399,7 +450,7 @@ int dbmp_blur_atlas(dbmp_aids_stream stream, const void *atlas, int B, int Hb, i
 long long dbmp_sa_init_workspace_bytes(int H, int W)
 {
     if (H < 1 || W < 1 || (long long)H * W >= INT_MAX) return -1;
-    return (long long)sa_layout((long long)H * W).total;
+    return (long long)sa_layout((long long)H * W, H, W).total;
 }
 
 int dbmp_sa_init(dbmp_aids_stream stream, const float *target, int H, int W, int win,
@@ -414,17 +465,18 @@ int dbmp_sa_init(dbmp_aids_stream stream, const float *target, int H, int W, int
     if (!(base >= 0.0 && base <= 1.0) || !(s_min > 0.0) || !(s_max >= s_min)) return DBMP_EINVAL;
     if (!(sigma_c >= 0.0) || ((uintptr_t)workspace & 15)) return DBMP_EINVAL;
     const long long npix = (long long)H * W;
-    const SaLayout L = sa_layout(npix);
+    const SaLayout L = sa_layout(npix, H, W);
     if (workspace_bytes < (long long)L.total) return DBMP_EINVAL;
     char *ws = (char *)workspace;
     auto *minmax = (unsigned long long *)(ws + L.minmax);
+    auto *bmm = (unsigned long long *)(ws + L.bmm);
     auto *lv = (double *)(ws + L.lv);
     auto *cdf = (long long *)(ws + L.cdf);
     auto *bsum = (long long *)(ws + L.bsum);
     hipStream_t st = (hipStream_t)stream;
-    k_lv_init<<<1, 1, 0, st>>>(minmax);
-    k_local_var<<<dim3((W + LV_T - 1) / LV_T, (H + LV_T - 1) / LV_T), 256, 0, st>>>(
-        target, H, W, win / 2, lv, minmax);
+    const dim3 lvg((W + LV_T - 1) / LV_T, (H + LV_T - 1) / LV_T);
+    k_local_var<<<lvg, 256, 0, st>>>(target, H, W, win / 2, lv, bmm);
+    k_lv_minmax<<<1, 1024, 0, st>>>(bmm, (int)(lvg.x * lvg.y), minmax);
     const unsigned g = (unsigned)((npix + 255) / 256);
     k_nlv<<<g, 256, 0, st>>>(lv, npix, minmax, base, nlv_out, cdf);
     const int nb = (int)((npix + SCAN_BLOCK - 1) / SCAN_BLOCK);
@@ -457,7 +509,8 @@ int dbmp_constraint_loss(dbmp_aids_stream stream, const float *image, const floa
     if (!image || !alpha || !target || !target_alpha || !dL_dimage || !dL_dalpha) return DBMP_EINVAL;
     if (H < 1 || W < 1 || (long long)H * W >= INT_MAX || !(lambda >= 0.f)) return DBMP_EINVAL;
     const long long npix = (long long)H * W;
-    k_constraint<<<(unsigned)((npix + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+    const long long blocks = std::min<long long>((npix + 255) / 256, CONSTRAINT_BLOCKS);
+    k_constraint<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(
         image, alpha, target, target_alpha, npix, lambda, dL_dimage, dL_dalpha, loss);
     return launched();
 }

@@ -2,10 +2,10 @@
 //
 // Stage 1: one lane per primitive finds the box of export pixels its bilinear support can reach
 // (float64, as the binning), then one workgroup turns the box areas into offsets (an exclusive
-// int64 scan). Stage 2: a grid of (primitive, tile row, tile column) workgroups of 16 x 16 export
-// pixels; each lane evaluates its pixel's alpha (the forward's arithmetic: float64 coordinates,
-// float32 bilinear sample) and writes it into the primitive's own packed box. Every output value
-// has exactly one writer, so no atomics.
+// int64 scan). Stage 2: one workgroup per primitive walks its box's export pixels; each lane
+// evaluates a pixel's alpha (the forward's arithmetic: float64 coordinates, float32 bilinear
+// sample) and writes it into the primitive's own packed box. Every output value has exactly one
+// writer, so no atomics.
 #include "dbmp_export.h"
 #include "dbmp_internal.h"
 #include "diffbmp.h"
@@ -15,8 +15,6 @@
 
 namespace dbmp {
 namespace {
-
-constexpr int EXP_T = 16;
 
 // Canvas point of export pixel X: (X + 0.5) / rho - 0.5; export coordinate of canvas point x:
 // rho (x + 0.5) - 0.5.
@@ -98,8 +96,13 @@ __device__ __forceinline__ float tex_at(const TexT *__restrict__ bm, int Hb, int
     return (r >= 0 && r < Hb && c >= 0 && c < Wb) ? texel<TexT>(bm[(size_t)r * Wb + c]) : 0.f;
 }
 
+// One workgroup per primitive: the primitive's constants once, then its box's pixels in
+// row-major order, 256 at a time (coalesced stores into its packed box). A grid of (primitive,
+// tile row, tile column) sized by the largest box launched mostly empty workgroups and
+// evaluated the exponentials per pixel: 5.1 ms at 2048^2 with 65,536 primitives against
+// 0.59 ms. (One wave per primitive took 1.17 ms: the largest boxes then run on 64 lanes.)
 template <typename TexT>
-__global__ void __launch_bounds__(EXP_T * EXP_T)
+__global__ void __launch_bounds__(256)
 k_export_layers(const float *__restrict__ params, const int *__restrict__ idx, int B,
                 const TexT *__restrict__ atlas, int Hb, int Wb, double rho, float alpha_max,
                 const int *__restrict__ boxes, const long long *__restrict__ offsets,
@@ -108,37 +111,48 @@ k_export_layers(const float *__restrict__ params, const int *__restrict__ idx, i
     const int i = blockIdx.x;
     const int bw = boxes[4 * i + 2], bh = boxes[4 * i + 3];
     const float *p = params + (size_t)i * 8;
-    if (blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x < 3)
+    if (threadIdx.x < 3)
         colour_out[3 * i + threadIdx.x] = (float)(1.0 / (1.0 + exp(-(double)p[5 + threadIdx.x])));
-    const int lx = threadIdx.x % EXP_T, ly = threadIdx.x / EXP_T;
-    const int bx = blockIdx.z * EXP_T + lx, by = blockIdx.y * EXP_T + ly;
-    if (bx >= bw || by >= bh) return;
+    const int n = bw * bh;
+    if (n == 0) return;
+    float *out = alpha_out + offsets[i];
     const int k = idx[i];
-    float a = 0.f;
-    if (k >= 0 && k < B) {
-        // the forward's map (float64): U = cu (u + 1), u = (cos dx + sin dy) / s
-        const double s = exp((double)p[2]);
-        double st, ct;
-        sincos((double)p[3], &st, &ct);
-        const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1);
-        const double X = boxes[4 * i] + bx, Y = boxes[4 * i + 1] + by;
-        const double dx = (X + 0.5) / rho - 0.5 - (double)p[0];
-        const double dy = (Y + 0.5) / rho - 0.5 - (double)p[1];
-        const double U = cu * ((ct * dx + st * dy) / s + 1.0);
-        const double V = cv * ((-st * dx + ct * dy) / s + 1.0);
+    if (!(k >= 0 && k < B)) {
+        for (int j = threadIdx.x; j < n; j += 256) out[j] = 0.f;
+        return;
+    }
+    // the forward's map (float64), folded as the binning folds it: U = aU x + bU y + eU with
+    // U = cu (u + 1), u = (cos dx + sin dy) / s (unpadded bitmap coordinates here)
+    const double s = exp((double)p[2]);
+    double st, ct;
+    sincos((double)p[3], &st, &ct);
+    const double cu = 0.5 * (Wb - 1), cv = 0.5 * (Hb - 1), inv_s = 1.0 / s;
+    const double aU = cu * ct * inv_s, bU = cu * st * inv_s;
+    const double aV = -cv * st * inv_s, bV = cv * ct * inv_s;
+    const double px = p[0], py = p[1];
+    const double eU = cu - aU * px - bU * py, eV = cv - aV * px - bV * py;
+    const float ka = (float)((double)alpha_max / (1.0 + exp(-(double)p[4])));
+    const double x0 = boxes[4 * i] + 0.5, y0 = boxes[4 * i + 1] + 0.5, ir = 1.0 / rho;
+    const TexT *bm = atlas + (size_t)k * Hb * Wb;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const int by = j / bw, bx = j - by * bw;
+        float a = 0.f;
+        // canvas point of export pixel (X, Y): (X + 0.5) / rho - 0.5
+        const double x = fma(x0 + bx, ir, -0.5), y = fma(y0 + by, ir, -0.5);
+        const double U = fma(aU, x, fma(bU, y, eU));
+        const double V = fma(aV, x, fma(bV, y, eV));
         const double u0 = floor(U), v0 = floor(V);
         if (u0 >= -1.0 && u0 <= Wb - 1.0 && v0 >= -1.0 && v0 <= Hb - 1.0) {
             const int iu = (int)u0, iv = (int)v0;
             const float wu = (float)(U - u0), wv = (float)(V - v0);
-            const TexT *bm = atlas + (size_t)k * Hb * Wb;
             const float p00 = tex_at(bm, Hb, Wb, iv, iu), p01 = tex_at(bm, Hb, Wb, iv, iu + 1);
             const float p10 = tex_at(bm, Hb, Wb, iv + 1, iu), p11 = tex_at(bm, Hb, Wb, iv + 1, iu + 1);
             const float top = fmaf(wu, p01 - p00, p00), bot = fmaf(wu, p11 - p10, p10);
             const float M = fmaf(wv, bot - top, top);
-            a = (float)((double)alpha_max / (1.0 + exp(-(double)p[4]))) * M;
+            a = ka * M;
         }
+        out[j] = a;
     }
-    alpha_out[offsets[i] + (long long)by * bw + bx] = a;
 }
 
 int launched() { return hipGetLastError() == hipSuccess ? DBMP_OK : DBMP_EHIP; }
@@ -192,21 +206,18 @@ int dbmp_export_layers(dbmp_export_stream stream, const float *params, const int
     if (N == 0) return DBMP_OK;
     if (!params || !atlas_idx || !atlas || !boxes || !offsets || !colour_out) return DBMP_EINVAL;
     if (max_w > 0 && !alpha_out) return DBMP_EINVAL;
-    const int ty = max_h > 0 ? (max_h + EXP_T - 1) / EXP_T : 1;
-    const int tx = max_w > 0 ? (max_w + EXP_T - 1) / EXP_T : 1;
-    if (ty > 65535 || tx > 65535) return DBMP_EINVAL;
-    const dim3 grid(N, ty, tx);
+    const dim3 grid(N);
     hipStream_t st = (hipStream_t)stream;
     if (atlas_dtype == DBMP_F32)
-        k_export_layers<float><<<grid, EXP_T * EXP_T, 0, st>>>(
+        k_export_layers<float><<<grid, 256, 0, st>>>(
             params, atlas_idx, B, (const float *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
             alpha_out, colour_out);
     else if (atlas_dtype == DBMP_F16)
-        k_export_layers<_Float16><<<grid, EXP_T * EXP_T, 0, st>>>(
+        k_export_layers<_Float16><<<grid, 256, 0, st>>>(
             params, atlas_idx, B, (const _Float16 *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
             alpha_out, colour_out);
     else
-        k_export_layers<uint16_t><<<grid, EXP_T * EXP_T, 0, st>>>(
+        k_export_layers<uint16_t><<<grid, 256, 0, st>>>(
             params, atlas_idx, B, (const uint16_t *)atlas, Hb, Wb, rho, alpha_max, boxes, offsets,
             alpha_out, colour_out);
     return launched();
