@@ -446,6 +446,11 @@ def bench_aids(capi, wl, d, p0, idx, atlas, target, np, torch, dev):
     t = timed(lambda: aids.sa_init(target, N, 4.0, 24.0, nu_init=-4.0, draws=draws), reps=5)
     out["sa_init"] = row(t, 16 * HW + 32 * N, "target read, NLV written, parameters written "
                                               "(the scan's workspace traffic not counted)")
+    bx_ = torch.empty(N, 4, dtype=torch.int32, device=dev)
+    of_ = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    wh_ = torch.empty(2, dtype=torch.int32, device=dev)
+    t = timed(lambda: aids.dbmp_export_boxes(sh, p0, N, Hb, Wb, H, W, 1.0, bx_, of_, wh_))
+    out["export_boxes_rho1"] = row(t, 56 * N, "parameters read, boxes and offsets written")
     boxes, offs, al, col = aids.export_layers(p0, idx, atlas, H, W, rho=1.0)
     total = int(offs[N].item())
     mw, mh = int(boxes[:, 2].max().item()), int(boxes[:, 3].max().item())

@@ -23,8 +23,8 @@ k_export_boxes(const float *__restrict__ params, int N, int Hb, int Wb, int HH, 
                double rho, int *__restrict__ boxes, long long *__restrict__ area,
                int *__restrict__ max_wh)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
+    const int i0 = blockIdx.x * 256 + threadIdx.x;
+    const int i = i0 < N ? i0 : N - 1;  // lanes past N repeat the last row (no store below)
     const float *p = params + (size_t)i * 8;
     bool fin = true;
     for (int q = 0; q < 8; ++q) fin = fin && isfinite(p[q]);
@@ -51,9 +51,17 @@ k_export_boxes(const float *__restrict__ params, int N, int Hb, int Wb, int HH, 
             w = (int)(fx1 - fx0) + 1; h = (int)(fy1 - fy0) + 1;
         }
     }
-    boxes[4 * i + 0] = x0; boxes[4 * i + 1] = y0; boxes[4 * i + 2] = w; boxes[4 * i + 3] = h;
-    area[i] = (long long)w * h;
-    if (w) { atomicMax(max_wh, w); atomicMax(max_wh + 1, h); }
+    if (i0 < N) {
+        boxes[4 * i + 0] = x0; boxes[4 * i + 1] = y0; boxes[4 * i + 2] = w; boxes[4 * i + 3] = h;
+        area[i] = (long long)w * h;
+    }
+    // the largest box: a wave maximum, then one atomic per wave (one per lane on the same two
+    // addresses would serialise)
+    for (int o = 32; o > 0; o >>= 1) {
+        w = max(w, __shfl_xor(w, o));
+        h = max(h, __shfl_xor(h, o));
+    }
+    if ((threadIdx.x & 63) == 0 && w) { atomicMax(max_wh, w); atomicMax(max_wh + 1, h); }
 }
 
 __global__ void k_export_init(int *max_wh)
