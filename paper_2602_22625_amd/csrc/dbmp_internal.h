@@ -56,6 +56,8 @@ struct __attribute__((aligned(16))) PrimRec {
 };
 static_assert(sizeof(PrimRec) == 160, "PrimRec layout");
 static_assert(offsetof(PrimRec, px0) == 80, "the pixel box is read as one 16-byte vector");
+static_assert(offsetof(PrimRec, ka) == 96 && offsetof(PrimRec, cb) == 108,
+              "opacity and colour are read as one 16-byte vector");
 
 __device__ __forceinline__ int find_by_prim(const ImgDev *__restrict__ imgs, int n, long long g)
 {

@@ -47,6 +47,13 @@
 #include <algorithm>
 #include <type_traits>
 
+// x * y, except that 0 times anything (infinity and NaN included) is 0 (v_mul_legacy_f32). The
+// compiler's own intrinsic, not inline assembly, so that it sees the instruction: on gfx950 a
+// vector instruction that reads a reciprocal's result in the next cycle needs a wait state,
+// which the compiler inserts only for instructions it knows.
+extern "C" __device__ __attribute__((const)) float dbmp_mul_legacy(float, float) __asm(
+    "llvm.amdgcn.fmul.legacy");
+
 namespace dbmp {
 
 template <int TS>
@@ -316,7 +323,7 @@ __device__ __forceinline__ void bitonic_sort(int n, Get get, Set set, Sync sync)
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
 // Transposed butterfly: v_permlane32_swap leaves values 0-3 summed over lanes l and l^32 in the
@@ -472,7 +479,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          const TileGeom<TS> &tg, uint64_t vmask, float g0,
                                          float g1, float g2, float ga, float G0, float G1,
                                          float G2, int K, float TK, float *__restrict__ dparams,
-                                         double cu1, double cv1, float cu_cv, float cv_cu,
+                                         double cu1, double cv1, float cu_cv2, float cv_cu,
                                          int lane);
 
 template <int TS, typename TexT, bool BG_PP, bool FUSED, int LAUNCH>
@@ -486,7 +493,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
              unsigned long long *__restrict__ pair_counter, int sched, int grab,
              const int *__restrict__ order, int *__restrict__ queue,
              const float *__restrict__ target, float *__restrict__ loss_tile,
-             float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
+             float *__restrict__ dparams, double cu1, double cv1, float cu_cv2, float cv_cu,
              int *__restrict__ fit_state, int atl_bytes)
 {
     constexpr int NT = TS * TS, CAP = SortCap<TS>::v;
@@ -618,7 +625,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
             C0 = fmaf(w, r.cr, C0);
             C1 = fmaf(w, r.cg, C1);
             C2 = fmaf(w, r.cb, C2);
-            T = T * (1.f - a);
+            T = fmaf(-T, a, T);  // T (1 - alpha), rounded once
         };
         auto over = [&](int j, const PrimRec &r, const Cell<TexT> &c, uint64_t m) {
             over_m(j, r, blend<TexT>(c).m(), m);
@@ -715,7 +722,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                             C0 = fmaf(w, r.cr, C0);
                             C1 = fmaf(w, r.cg, C1);
                             C2 = fmaf(w, r.cb, C2);
-                            T = T * (1.f - a);
+                            T = fmaf(-T, a, T);
                         }
                     }
                 }
@@ -768,7 +775,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                       recs,
                                       atlas, Wp, zcell, tg, vmask, g0, g1, g2, 0.f, b0, b1,
                                       b2,
-                                      tg.valid ? K : -1, TK, dparams, cu1, cv1, cu_cv, cv_cu,
+                                      tg.valid ? K : -1, TK, dparams, cu1, cv1, cu_cv2, cv_cu,
                                       lane);
         else
             bwd_walk<NT, TexT, false, PIPE, LDSA>(n, [&](int j) { return ((volatile int *)seg)[j]; },
@@ -776,7 +783,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
                                       g0,
                                       g1, g2,
                                       0.f, b0, b1, b2, tg.valid ? K : -1, TK, dparams, cu1, cv1,
-                                      cu_cv, cv_cu, lane);
+                                      cu_cv2, cv_cu, lane);
         const float ws = wave_sum(sq);
         if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
         __syncthreads();
@@ -823,7 +830,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
                                          const TileGeom<TS> &tg, uint64_t vmask, float g0,
                                          float g1, float g2, float ga, float G0, float G1,
                                          float G2, int K, float TK, float *__restrict__ dparams,
-                                         double cu1, double cv1, float cu_cv, float cv_cu,
+                                         double cu1, double cv1, float cu_cv2, float cv_cu,
                                          int lane)
 {
     const double xd = tg.px, yd = tg.py;
@@ -859,20 +866,20 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
     // vector instructions issue for the whole wave either way)
     auto under_m = [&](int e, int j, float M, float MU, float MV, float Ub, float Vb) {
         const PrimRec &r = s_rec[e];
+        const float4 kc = *reinterpret_cast<const float4 *>(&r.ka);  // ka, cr, cg, cb: one read
         float d[8];
-        const float a = r.ka * M;
+        const float a = kc.x * M;
         const float m = 1.f - a;
-        // T_j = T_{j+1} / (1 - alpha_j): reciprocal with one Newton step (about 1 ulp; exactly 1
-        // where alpha = 0). In front of K, 1 - alpha_j >= TAU, so the clamp changes nothing
-        // there; behind K (running value 0) it keeps the reciprocal finite.
-        const float mc = fmaxf(m, 0x1p-126f);
-        float rc = __builtin_amdgcn_rcpf(mc);
-        rc = fmaf(rc, fmaf(-mc, rc, 1.f), rc);
-        const float Tj = j == K ? TK : Trun * rc;
+        // T_j = T_{j+1} / (1 - alpha_j) with the hardware reciprocal (1 ulp). In front of K,
+        // T_j (1 - alpha_j) >= TAU, so 1 - alpha_j > 0 and the reciprocal is finite. Behind K the
+        // running value is 0, and the legacy multiply (0 times anything is 0) keeps it 0 where
+        // alpha = 1 makes the reciprocal infinite.
+        const float Tr = dbmp_mul_legacy(Trun, __builtin_amdgcn_rcpf(m));
+        const float Tj = j == K ? TK : Tr;
         Trun = Tj;
         // g . (c_j - G): the colour's lead over the composite behind it, which also advances
         // g . G to the composite behind layer j - 1: g . (G + alpha (c - G))
-        const float lead = fmaf(g2, r.cb, fmaf(g1, r.cg, g0 * r.cr)) - gG;
+        const float lead = fmaf(g2, kc.w, fmaf(g1, kc.z, fmaf(g0, kc.y, -gG)));
         float dal = lead;
         if (HAS_GA) dal = fmaf(ga, Bk, dal);
         dal *= Tj;
@@ -885,7 +892,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
         d[0] = gU;
         d[1] = gV;
         d[2] = fmaf(gU, Ub, gV * Vb);
-        d[3] = fmaf(gU * cu_cv, Vb, -(gV * cv_cu * Ub));
+        d[3] = fmaf(gU * cu_cv2, Vb, -(gV * Ub));  // times cv_cu at the flush
         gG = fmaf(a, lead, gG);
         Bk *= m;
         // lane 8q holds the wave total of value q; eight lanes add into the entry's LDS slots.
@@ -893,6 +900,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
         // partials, 8 lanes per address, saves 4 instructions but serialised in the LDS atomic
         // unit: it made the 2048^2 fit step's raster launch twice as long.)
         const float tot = reduce8(d, lane);
+        asm volatile("" ::"v"(tot));  // formed on every lane: the last add stays fused with its DPP move
         if ((lane & 7) == 0)
             __hip_atomic_fetch_add(s_grad + e * 8 + (lane >> 3), tot, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -965,7 +973,7 @@ __device__ __forceinline__ void bwd_walk(int n, IdAt id_at, bool staged,
             if (q < 2)
                 x = -r.ka * fmaf(q == 0 ? r.faU : r.fbU, s0, (q == 0 ? r.faV : r.fbV) * s1);
             else
-                x = (q == 2 ? -r.ka : q == 3 ? r.ka : q == 4 ? r.kaom : q == 5 ? r.ccr
+                x = (q == 2 ? -r.ka : q == 3 ? r.ka * cv_cu : q == 4 ? r.kaom : q == 5 ? r.ccr
                      : q == 6 ? r.ccg : r.ccb) * v;
             s_grad[t] = 0.f;  // ready for the next batch
             if (x != 0.f) unsafeAtomicAdd(dparams + (size_t)r.id * 8 + q, x);
@@ -984,7 +992,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
              const int *__restrict__ saveK, const float *__restrict__ saveT,
              const float *__restrict__ gI, const float *__restrict__ target,
              float *__restrict__ loss_tile, const float *__restrict__ gA,
-             float *__restrict__ dparams, double cu1, double cv1, float cu_cv, float cv_cu,
+             float *__restrict__ dparams, double cu1, double cv1, float cu_cv2, float cv_cu,
              const int *__restrict__ flags, int sched, int grab,
              const int *__restrict__ order, int *__restrict__ queue, int atl_bytes)
 {
@@ -1038,7 +1046,7 @@ k_raster_bwd(const PrimRec *__restrict__ recs, const int *__restrict__ lists, in
                                         recs,
                                         atlas, Wp, zcell, tg, vmask, g0, g1, g2, ga, G0, G1, G2,
                                         K, TK,
-                                        dparams, cu1, cv1, cu_cv, cv_cu, lane);
+                                        dparams, cu1, cv1, cu_cv2, cv_cu, lane);
         if (MSE) {
             const float ws = wave_sum(sq);
             if (lane == 0) s_loss[threadIdx.x >> 6] = ws;
@@ -1110,7 +1118,8 @@ static void fwd_t(const RasterArgs &a, hipStream_t st)
         a.n_images, a.n_tiles, (const TexT *)a.atlas_pad, a.Wp, a.zcell, a.bg, a.image, a.alpha,
         a.saveK,
         a.saveT, a.flags, a.pair_counter, a.sched, a.grab, a.order, a.queue, a.target,
-        a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv), (float)(cv / cu),
+        a.loss_tile, a.dparams, cu + 1.0, cv + 1.0, (float)((cu / cv) * (cu / cv)),
+        (float)(cv / cu),
         a.fit_state, atl);
 }
 
@@ -1126,7 +1135,7 @@ static void bwd_t(const RasterArgs &a, hipStream_t st)
         (size_t)((atl + 15) & ~15), st, a.ev_start, a.ev_stop, a.recs, a.lists, a.list_cap, a.tile_len, a.imgs, a.n_images, a.n_tiles,
         (const TexT *)a.atlas_pad, a.Wp, a.zcell, a.bg, a.saveK, a.saveT, MSE ? a.image : a.gI,
         a.target,
-        a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)(cu / cv),
+        a.loss_tile, a.gA, a.dparams, cu + 1.0, cv + 1.0, (float)((cu / cv) * (cu / cv)),
         (float)(cv / cu), a.flags, a.sched, a.grab, a.order, a.queue + 2, atl);
 }
 
