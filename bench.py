@@ -305,7 +305,10 @@ def main():
     extra["c2_separate_calls"] = {
         "fwd_incl_binning_ms": round(f2 * 1e3, 4), "bwd_ms": round(b2 * 1e3, 4),
         "evals_per_pass": round(pp2), "fwd_plus_bwd_evals_per_s": round(pp2 / (f2 + b2)),
-        "peak_mem_GB": round(torch.cuda.max_memory_allocated() / 1e9, 3),
+        "peak_mem_GB": round((torch.cuda.max_memory_allocated() + R2.workspace_bytes()) / 1e9,
+                             3),
+        "peak_mem_what": "torch's peak allocation over the run (inputs, image, target, "
+                         "gradients, Adam state) plus the library's workspace",
         "paper_table2_2048sq_T32_fwd_bwd_ms": {k: {"fwd": v[0], "bwd": v[1]}
                                                for k, v in PAPER_TABLE2_2048.items()},
         "note": "the paper times its renderer's kernels alone (binning on the CPU, excluded) "

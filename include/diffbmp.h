@@ -326,6 +326,11 @@ long long dbmp_support_pairs(dbmp_ctx *ctx, dbmp_stream stream, int reset);
  * addresses and must be captured again; compare the epoch at capture and before a replay. */
 long long dbmp_workspace_epoch(const dbmp_ctx *ctx);
 
+/* Device bytes the context's workspace holds now (records, tile lists and counters, the per-pixel
+ * (K, T_K), the padded atlas, descriptors and flags); -1 for a NULL context. Memory the caller
+ * passes in (parameters, images, gradients) is not included. */
+long long dbmp_workspace_bytes(const dbmp_ctx *ctx);
+
 /* Message of the last error on this context ("" if none). Valid until the next call. */
 const char *dbmp_last_error(const dbmp_ctx *ctx);
 

@@ -72,6 +72,7 @@ def load():
         "dbmp_support_pairs": ([P, P, I], LL),
         "dbmp_last_error": ([P], ctypes.c_char_p),
         "dbmp_workspace_epoch": ([P], LL),
+        "dbmp_workspace_bytes": ([P], LL),
         "dbmp_render_mse_noalloc": ([P, P, P, I, P, I, I, I, I, I, I, P, I, F, I, I, P, P, P, I,
                                      P, ctypes.POINTER(ctypes.c_size_t)], I),
         "dbmp_mse_grad": ([P, P, P, LL, P, P], I),
@@ -265,6 +266,10 @@ def dbmp_last_error(ctx):
 
 def dbmp_workspace_epoch(ctx):
     return int(load().dbmp_workspace_epoch(ctx))
+
+
+def dbmp_workspace_bytes(ctx):
+    return int(load().dbmp_workspace_bytes(ctx))
 
 
 def dbmp_mse_grad(stream, image, target, n, grad, loss):

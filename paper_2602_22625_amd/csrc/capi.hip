@@ -689,6 +689,18 @@ long long dbmp_support_pairs(dbmp_ctx *c, dbmp_stream stream, int reset)
 
 long long dbmp_workspace_epoch(const dbmp_ctx *c) { return c ? c->epoch : -1; }
 
+long long dbmp_workspace_bytes(const dbmp_ctx *c)
+{
+    if (!c) return -1;
+    const Buf *bufs[] = {&c->recs,      &c->tile_count, &c->tile_len,  &c->lists,
+                         &c->saveK,     &c->saveT,      &c->atlas_pad, &c->box,
+                         &c->imgs,      &c->flags,      &c->counter,   &c->list_max,
+                         &c->loss_tile, &c->order,      &c->order_hist, &c->queue};
+    long long n = 0;
+    for (const Buf *b : bufs) n += (long long)b->cap;
+    return n;
+}
+
 const char *dbmp_last_error(const dbmp_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 }  // extern "C"

@@ -370,6 +370,10 @@ class Renderer:
     def longest_list(self):
         return capi.dbmp_longest_list(self.ctx, capi.stream_handle())
 
+    def workspace_bytes(self):
+        """Device bytes the library's own workspace holds (not counted by torch's allocator)."""
+        return capi.dbmp_workspace_bytes(self.ctx)
+
 
 class RenderFn(torch.autograd.Function):
     """(image, alpha) = RenderFn.apply(params, renderer, atlas_idx, atlas, H, W, bg, alpha_max,

@@ -100,9 +100,15 @@ def check_fd():
     loss = ((img - tgt) ** 2).mean()
     loss.backward()
     torch.cuda.synchronize()
-    peak = torch.cuda.max_memory_allocated() - base
-    print("peak memory of forward + backward: %.3f GB" % (peak / 1e9), flush=True)
-    assert peak < 0.5e9, peak  # O(HW + N + pairs): image, target, gradients, lists
+    ws = R.workspace_bytes()
+    peak = torch.cuda.max_memory_allocated() - base + ws
+    print("peak memory of forward + backward: %.3f GB (library workspace %.3f GB)"
+          % (peak / 1e9, ws / 1e9), flush=True)
+    # O(HW + N + pairs): inputs, target, image, alpha and this loss's autograd temporaries (torch's
+    # allocator, about 0.38 GB: several 50 MB image-sized tensors) and the library's records,
+    # lists, per-pixel (K, T_K) and padded atlas (about 0.08 GB). A per-layer cache would need
+    # gigabytes here.
+    assert peak < 0.6e9, peak
     g = p.grad.detach().cpu().numpy().astype(np.float64)
     R.check()
 

@@ -96,6 +96,8 @@ def test_host_argument_checks_need_no_device():
     assert lib.dbmp_set_atlas(None, None, None, 1, 2, 2, 0) == capi.DBMP_EINVAL
     assert lib.dbmp_mse_loss(None, None, None) == capi.DBMP_EINVAL
     assert lib.dbmp_longest_list(None, None) == -1
+    assert lib.dbmp_workspace_epoch(None) == -1
+    assert lib.dbmp_workspace_bytes(None) == -1
     assert lib.dbmp_set_schedule(None, 1, 4, 1) == capi.DBMP_EINVAL
     assert lib.dbmp_set_atlas_placement(None, 1) == capi.DBMP_EINVAL
     assert lib.dbmp_fit_step(None, None, None, None, 0, 4, 4, None, 0, 1.0, 16, None, None,

@@ -315,6 +315,31 @@ def test_list_overflow_is_reported_then_grown():
     assert torch.equal(img, img2)
 
 
+def test_workspace_bytes_cover_the_per_primitive_and_per_pixel_state():
+    """dbmp_workspace_bytes reports the library's own device memory: at least the records
+    (160 B per primitive), the per-pixel (K, T_K) and the padded atlas of the last render, and it
+    only grows (with the workspace epoch) when a larger canvas needs more."""
+    from paper_2602_22625_amd import capi
+    from paper_2602_22625_amd.render import Renderer
+    d = synth.make_workload("c0")
+    p, idx, a = to_dev(d)
+    R0 = Renderer()
+    assert R0.workspace_bytes() >= 0
+    bg = torch.ones(3, device="cuda")
+    R0.render(p, idx, a, 128, 128, bg, 1.0, 16)
+    R0.check()
+    b1, e1 = R0.workspace_bytes(), capi.dbmp_workspace_epoch(R0.ctx)
+    padded = (32 + 2) * (32 + 2) * 4
+    assert b1 >= 160 * 64 + 8 * 128 * 128 + padded
+    assert b1 < 4 * (160 * 64 + 8 * 128 * 128 + padded) + (1 << 20)
+    R0.render(p, idx, a, 128, 128, bg, 1.0, 16)  # same size: nothing grows
+    assert R0.workspace_bytes() == b1 and capi.dbmp_workspace_epoch(R0.ctx) == e1
+    R0.render(p, idx, a, 512, 512, bg, 1.0, 16)
+    R0.check()
+    assert R0.workspace_bytes() >= b1 + 8 * (512 * 512 - 128 * 128)
+    assert capi.dbmp_workspace_epoch(R0.ctx) > e1
+
+
 # (schedule, workgroups per CU, items per grab)
 SCHEDULES = [(0, 4, 1), (1, 4, 1), (2, 1, 1), (2, 8, 16), (2, 4, 0)]
 
