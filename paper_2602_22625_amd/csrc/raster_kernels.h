@@ -502,7 +502,7 @@ k_raster_fwd(const PrimRec *__restrict__ recs, int *__restrict__ lists, int list
     constexpr bool PIPE = LAUNCH == LAUNCH_TILE_PIPE || LDSA;
     // the fused step keeps its first visits' bilinear values for the backward (the pipelined
     // build runs where the grid leaves SIMDs with few waves, so registers are not its limit)
-    constexpr int SVN = LAUNCH == LAUNCH_TILE
+    constexpr int SVN = (LAUNCH == LAUNCH_TILE || LAUNCH == LAUNCH_PERSISTENT)
                             ? (is_f16<TexT> ? STORED_VISITS_F16 : STORED_VISITS)
                         : PIPE ? (is_f16<TexT> ? STORED_VISITS_PIPE_F16 : STORED_VISITS_PIPE)
                                : 0;
